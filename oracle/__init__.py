@@ -1,0 +1,194 @@
+"""Plain FP64 CPU oracle for the simulated oscillator Ising/Potts machine.
+
+TEST INFRASTRUCTURE ONLY: imported by the test suite, the smoke check and the
+CPU-baseline leg of the benchmark, never by the product package.  It shares no
+code with the GPU library; the only thing both sides use is the seeded input
+generator module ``synth``.
+
+The arithmetic lives in ``oracle.c`` (FP64, Algorithm 1 / Eq. 5 of the paper,
+Philox4x32-10 + Box-Muller noise); this module marshals numpy arrays into it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_lib = None
+
+_i32, _i64, _u32, _u64, _f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
+                                ctypes.c_uint64, ctypes.c_double)
+_P = ctypes.c_void_p
+
+
+def lib():
+    """Load liboracle.so, compiling it with gcc first if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        L.orc_philox4x32_10.argtypes = [_P, _P, _P]
+        L.orc_philox4x32_10.restype = None
+        L.orc_normal.argtypes = [_u64, _u32, _u32]
+        L.orc_normal.restype = _f64
+        L.orc_normals.argtypes = [_u64, _u32, _i64, _u32, _P]
+        L.orc_normals.restype = None
+        L.orc_run_csr.argtypes = [_i32, _P, _P, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P,
+                                  _P, _i32]
+        L.orc_run_csr.restype = ctypes.c_int
+        L.orc_run_dense.argtypes = [_i32, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P, _P,
+                                    _i32]
+        L.orc_run_dense.restype = ctypes.c_int
+        L.orc_round_f32.argtypes = [_i64, _P, _i32, _P]
+        L.orc_round_f32.restype = None
+        L.orc_cut_int.argtypes = [_i32, _P, _P, _P, _P]
+        L.orc_cut_int.restype = _i64
+        L.orc_cut_f64.argtypes = [_i32, _P, _P, _P, _P]
+        L.orc_cut_f64.restype = _f64
+        L.orc_conflicts.argtypes = [_i32, _P, _P, _P, _P]
+        L.orc_conflicts.restype = _i64
+        L.orc_h_model.argtypes = [_i32, _P, _P, _P, _i32, _P]
+        L.orc_h_model.restype = _f64
+        L.orc_h_eq6.argtypes = [_i32, _P, _P, _P, _P]
+        L.orc_h_eq6.restype = _f64
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ---------------------------------------------------------------- noise ----
+def philox4x32_10(ctr, key) -> np.ndarray:
+    """Philox4x32-10 block function (Salmon et al., SC'11)."""
+    c = _c(ctr, np.uint32)
+    k = _c(key, np.uint32)
+    assert c.shape == (4,) and k.shape == (2,)
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def normal(seed: int, i: int, t: int) -> float:
+    """The standard normal that drives oscillator i at global step t."""
+    return lib().orc_normal(int(seed), int(i), int(t))
+
+
+def normals(seed: int, i0: int, count: int, t: int) -> np.ndarray:
+    out = np.zeros(int(count), np.float64)
+    lib().orc_normals(int(seed), int(i0), int(count), int(t), _ptr(out))
+    return out
+
+
+# ----------------------------------------------------------- integrator ----
+def _sched(a, steps):
+    a = _c(a, np.float64)
+    if a.shape != (steps,):
+        raise ValueError(f"schedule must have shape ({steps},), got {a.shape}")
+    return a
+
+
+def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
+    """Integrate Eq. 5 (Algorithm 1) on a CSR coupling; returns theta [R][n] in FP64."""
+    rp = _c(row_ptr, np.int64)
+    cl = _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    th = np.array(theta0, dtype=np.float64, order="C", copy=True)
+    if th.ndim == 1:
+        th = th[None, :]
+    R, n = th.shape
+    steps = len(K)
+    sd = _c(seeds, np.uint64)
+    assert sd.shape == (R,) and rp.shape == (n + 1,)
+    rc = lib().orc_run_csr(n, _ptr(rp), _ptr(cl), _ptr(Jv), int(q), R, steps, int(step0),
+                           float(dt), _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
+                           _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_run_csr rejected its arguments")
+    return th
+
+
+def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
+    """Integrate Eq. 5 with the all-pairs (dense) coupling sum, diagonal ignored."""
+    Jd = _c(J, np.float64)
+    th = np.array(theta0, dtype=np.float64, order="C", copy=True)
+    if th.ndim == 1:
+        th = th[None, :]
+    R, n = th.shape
+    assert Jd.shape == (n, n)
+    steps = len(K)
+    sd = _c(seeds, np.uint64)
+    rc = lib().orc_run_dense(n, _ptr(Jd), int(q), R, steps, int(step0), float(dt),
+                             _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
+                             _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_run_dense rejected its arguments")
+    return th
+
+
+# -------------------------------------------------------------- readout ----
+def round_f32(theta, q) -> np.ndarray:
+    """Nearest stable phase index k = floor(q theta / 2 pi + 1/2) mod q (FP32 decision)."""
+    th = _c(theta, np.float32)
+    out = np.zeros(th.shape, np.int8)
+    lib().orc_round_f32(th.size, _ptr(th), int(q), _ptr(out))
+    return out
+
+
+def dense_to_csr(J):
+    """Off-diagonal nonzeros of a dense coupling as (row_ptr, col, values)."""
+    J = np.asarray(J, dtype=np.float64)
+    n = J.shape[0]
+    mask = J != 0.0
+    np.fill_diagonal(mask, False)
+    rows, cols = np.nonzero(mask)
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.add.at(row_ptr, rows + 1, 1)
+    return np.cumsum(row_ptr), cols.astype(np.int32), J[rows, cols]
+
+
+def cut_int(row_ptr, col, J, colour) -> int:
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Ji = _c(J, np.int64)
+    co = _c(colour, np.int8)
+    return int(lib().orc_cut_int(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Ji), _ptr(co)))
+
+
+def cut_f64(row_ptr, col, J, colour) -> float:
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    co = _c(colour, np.int8)
+    return float(lib().orc_cut_f64(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Jv), _ptr(co)))
+
+
+def conflicts(row_ptr, col, J, colour) -> int:
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    co = _c(colour, np.int8)
+    return int(lib().orc_conflicts(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Jv), _ptr(co)))
+
+
+def h_model(row_ptr, col, J, q, colour) -> float:
+    """Eq. 1 (q = 2) or Eq. 2 (q >= 3) at the given colours."""
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    co = _c(colour, np.int8)
+    return float(lib().orc_h_model(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Jv), int(q), _ptr(co)))
+
+
+def h_eq6(row_ptr, col, J, theta) -> float:
+    """Eq. 6 with w = -J at continuous phases theta (radians)."""
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    th = _c(theta, np.float64)
+    return float(lib().orc_h_eq6(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Jv), _ptr(th)))

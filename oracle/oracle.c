@@ -1,0 +1,248 @@
+/*
+ * oracle.c -- plain FP64 CPU reference of the simulated oscillator Ising/Potts
+ * machine (arXiv 2505.22631).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path links, loads or calls
+ * this file; only the test suite, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no source, header, table or constant with the
+ * GPU library.
+ *
+ * What it computes, in the paper's order (Algorithm 1, Sec. II-E Eq. 5):
+ *   for each step t: first every oscillator's coupling sum is formed from the
+ *   phases of step t (the derivative loop), then every phase is advanced by
+ *   forward Euler with the SHIL term and a Gaussian noise kick and wrapped back
+ *   into one period (the update loop).
+ *
+ * Readings of the paper that this file follows (all phases in radians, period
+ * 2*pi; the paper's normalised phase is theta / (2*pi)):
+ *   - J is the Ising coupling of Eq. 1 (H = -sum_{i<j} J_ij s_i s_j); max-cut
+ *     maps to J = -w (Sec. II-C).  The drift that descends this energy is
+ *       f_i = -K * sum_{j != i} J_ij sin(theta_i - theta_j) - Ks sin(q theta_i)
+ *     (the sign printed in Eq. 5 would synchronise max-cut edge partners; the
+ *     descent sign is the one whose fixed points minimise Eq. 1 / Eq. 6).
+ *   - SHIL: -Ks sin(q theta) has its stable points at 2*pi*k/q (Sec. II-D).
+ *   - Noise: theta += sigma_t * sqrt(dt) * xi, xi ~ N(0,1) (the Algorithm 1
+ *     form, sigma playing the role of K_n).
+ *   - Schedules K, Ks, sigma are per-step arrays indexed by the local step.
+ *   - The noise is a counter-based stream: Philox4x32-10 (Salmon, Moraes, Dror,
+ *     Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11) keyed by the
+ *     replica's 64-bit seed, counter (i/4, t, 0, 0), followed by Box-Muller
+ *     (Box & Muller 1958) on 24-bit uniforms.  Words (x0,x1) serve oscillators
+ *     i = 0,1 mod 4 and (x2,x3) serve i = 2,3 mod 4; the even member of a pair
+ *     takes rho*cos(2 pi u2), the odd one rho*sin(2 pi u2).
+ *   - Thresholding (readout only, never fed back): k = floor(q theta/(2 pi) + 1/2)
+ *     mod q, evaluated in FP32 as floor(fmaf(theta, (float)(q/(2 pi)), 0.5f)),
+ *     the precision the GPU takes the same decision in.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_TWO_PI 6.283185307179586476925286766559
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11, Sec. 4.2): ten rounds of two 32x32->64 products     */
+/* with the Weyl-sequence key schedule.                                      */
+/* ------------------------------------------------------------------------ */
+static void philox_one_round(uint32_t x[4], const uint32_t k[2]) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t y0 = hi1 ^ x[1] ^ k[0];
+    const uint32_t y1 = lo1;
+    const uint32_t y2 = hi0 ^ x[3] ^ k[1];
+    const uint32_t y3 = lo0;
+    x[0] = y0; x[1] = y1; x[2] = y2; x[3] = y3;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t x[4] = {ctr[0], ctr[1], ctr[2], ctr[3]};
+    uint32_t k[2] = {key[0], key[1]};
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k[0] += 0x9E3779B9u; /* golden ratio */
+            k[1] += 0xBB67AE85u; /* sqrt(3) - 1  */
+        }
+        philox_one_round(x, k);
+    }
+    memcpy(out, x, sizeof x);
+}
+
+/* One standard normal for oscillator i at global step t of the replica whose
+ * seed is `seed`. */
+double orc_normal(uint64_t seed, uint32_t i, uint32_t t) {
+    const uint32_t ctr[4] = {i >> 2, t, 0u, 0u};
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    const int pair = (int)((i >> 1) & 1u);
+    const uint32_t xa = x[2 * pair], xb = x[2 * pair + 1];
+    const double u1 = ((double)(xa >> 8) + 1.0) / 16777216.0; /* (0, 1] */
+    const double u2 = (double)(xb >> 8) / 16777216.0;         /* [0, 1) */
+    const double rho = sqrt(-2.0 * log(u1));
+    return (i & 1u) ? rho * sin(ORC_TWO_PI * u2) : rho * cos(ORC_TWO_PI * u2);
+}
+
+void orc_normals(uint64_t seed, uint32_t i0, int64_t count, uint32_t t, double* out) {
+    for (int64_t k = 0; k < count; ++k) out[k] = orc_normal(seed, (uint32_t)(i0 + k), t);
+}
+
+static double wrap_2pi(double th) {
+    double w = th - ORC_TWO_PI * floor(th / ORC_TWO_PI);
+    if (w >= ORC_TWO_PI) w -= ORC_TWO_PI;
+    if (w < 0.0) w = 0.0;
+    return w;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integrators.  theta is [R][n], FP64, in/out.  J is the Ising coupling.    */
+/* Returns 0, or -1 on a bad argument.                                       */
+/* ------------------------------------------------------------------------ */
+static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* Jv,
+                      const double* Jdense, int32_t q, int32_t R, int32_t steps, int64_t step0,
+                      double dt, const double* K, const double* Ks, const double* sigma,
+                      const uint64_t* seeds, double* theta, int32_t nthreads) {
+    if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0)) return -1;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t r = 0; r < R; ++r) {
+        double* th = theta + (int64_t)r * n;
+        double* coup = (double*)malloc(sizeof(double) * (size_t)n);
+        if (!coup) { bad = 1; continue; }
+        for (int32_t s = 0; s < steps; ++s) {
+            const uint32_t t = (uint32_t)(step0 + s);
+            /* derivative loop: every coupling sum from the phases of step t */
+            for (int32_t i = 0; i < n; ++i) {
+                double acc = 0.0;
+                if (Jdense) {
+                    for (int32_t j = 0; j < n; ++j)
+                        if (j != i) acc += Jdense[(int64_t)i * n + j] * sin(th[i] - th[j]);
+                } else {
+                    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                        acc += Jv[e] * sin(th[i] - th[col[e]]);
+                }
+                coup[i] = acc;
+            }
+            /* update loop: forward Euler + SHIL + noise, then wrap */
+            const double sq = sqrt(dt);
+            for (int32_t i = 0; i < n; ++i) {
+                const double f = -K[s] * coup[i] - Ks[s] * sin((double)q * th[i]);
+                const double xi = orc_normal(seeds[r], (uint32_t)i, t);
+                th[i] = wrap_2pi(th[i] + dt * f + sigma[s] * sq * xi);
+            }
+        }
+        free(coup);
+    }
+    return bad ? -1 : 0;
+}
+
+int orc_run_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                int32_t q, int32_t R, int32_t steps, int64_t step0, double dt, const double* K,
+                const double* Ks, const double* sigma, const uint64_t* seeds, double* theta,
+                int32_t nthreads) {
+    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+                      theta, nthreads);
+}
+
+int orc_run_dense(int32_t n, const double* J, int32_t q, int32_t R, int32_t steps, int64_t step0,
+                  double dt, const double* K, const double* Ks, const double* sigma,
+                  const uint64_t* seeds, double* theta, int32_t nthreads) {
+    return run_common(n, NULL, NULL, NULL, J, q, R, steps, step0, dt, K, Ks, sigma, seeds, theta,
+                      nthreads);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thresholding (Sec. III-B "phase threshold"): nearest of the q stable      */
+/* phases 2 pi k / q.  FP32 decision; -1 for non-finite or |theta| >= 2^20.  */
+/* ------------------------------------------------------------------------ */
+void orc_round_f32(int64_t count, const float* theta, int32_t q, int8_t* colour) {
+    const float scale = (float)((double)q / ORC_TWO_PI);
+    for (int64_t k = 0; k < count; ++k) {
+        const float th = theta[k];
+        if (!isfinite(th) || fabsf(th) >= 1048576.0f) { colour[k] = -1; continue; }
+        const float x = floorf(fmaf(th, scale, 0.5f));
+        int64_t c = (int64_t)x % q;
+        if (c < 0) c += q;
+        colour[k] = (int8_t)c;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Readouts over the upper triangle i < j of a symmetric CSR coupling.       */
+/* ------------------------------------------------------------------------ */
+/* max-cut value with edge weights w = -J (Sec. II-C), integer weights */
+int64_t orc_cut_int(int32_t n, const int64_t* row_ptr, const int32_t* col, const int64_t* Jint,
+                    const int8_t* colour) {
+    int64_t cut = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (i < j && colour[i] != colour[j]) cut += -Jint[e];
+        }
+    return cut;
+}
+
+double orc_cut_f64(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                   const int8_t* colour) {
+    double cut = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (i < j && colour[i] != colour[j]) cut += -J[e];
+        }
+    return cut;
+}
+
+/* colouring conflicts: edges (J != 0) whose ends share a colour */
+int64_t orc_conflicts(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                      const int8_t* colour) {
+    int64_t c = 0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (i < j && J[e] != 0.0 && colour[i] == colour[j]) ++c;
+        }
+    return c;
+}
+
+/* Eq. 1 for q = 2 (spin s = 1 - 2k), Eq. 2 for q >= 3 (Kronecker delta). */
+double orc_h_model(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                   int32_t q, const int8_t* colour) {
+    double h = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (i >= j) continue;
+            if (q == 2) {
+                const double si = 1.0 - 2.0 * colour[i], sj = 1.0 - 2.0 * colour[j];
+                h -= J[e] * si * sj;
+            } else if (colour[i] == colour[j]) {
+                h -= J[e];
+            }
+        }
+    return h;
+}
+
+/* Eq. 6 with the weights w = -J, evaluated at the (continuous) phases. */
+double orc_h_eq6(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                 const double* theta) {
+    double h = 0.0;
+    for (int32_t i = 0; i < n; ++i)
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (i < j) h += -J[e] * cos(theta[i] - theta[j]);
+        }
+    return h;
+}
+
+int orc_abi_version(void) { return 1; }

@@ -1,0 +1,167 @@
+"""Pins of the oracle's integrator (Eq. 5 / Algorithm 1 with the readings
+stated in oracle.c) against closed forms and invariants of the dynamics."""
+import numpy as np
+import pytest
+
+import synth
+
+TWO_PI = 2 * np.pi
+
+
+def _pair():
+    # one max-cut edge of weight 1  ->  Ising coupling J = -1
+    return np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([-1.0, -1.0])
+
+
+def _wrapdiff(a, b):
+    d = np.mod(a - b, TWO_PI)
+    return np.minimum(d, TWO_PI - d)
+
+
+def test_noise_only_is_sum_of_kicks(orc):
+    # K = Ks = 0: theta_T = wrap(theta_0 + sum_t sigma_t sqrt(dt) xi_t)
+    g = synth.random_small(9, 0.5, seed=1, weights="int")
+    steps, dt = 25, 0.01
+    th0 = synth.theta0(3, 9, seed=2)
+    sig = synth.ramp(0.05, 0.3, steps)
+    sd = np.array([3, 1 << 33, 12345], np.uint64)
+    out = orc.run_csr(g.row_ptr, g.col, -g.w, th0, q=2, dt=dt, K=np.zeros(steps),
+                      Ks=np.zeros(steps), sigma=sig, seeds=sd, step0=7)
+    for r in range(3):
+        acc = th0[r].astype(np.float64).copy()
+        for s in range(steps):
+            acc += float(sig[s]) * np.sqrt(dt) * orc.normals(int(sd[r]), 0, 9, 7 + s)
+        assert np.max(_wrapdiff(out[r], np.mod(acc, TWO_PI))) < 1e-12
+        assert np.all((out[r] >= 0) & (out[r] < TWO_PI))
+
+
+@pytest.mark.parametrize("K", [0.7, 2.0])
+def test_pair_closed_form_and_first_order(orc, K):
+    # For J = -1 the phase difference d obeys d' = 2K sin d, solved by
+    # tan(d/2) = tan(d0/2) exp(2 K t): the edge is driven to anti-phase (cut).
+    rp, cl, J = _pair()
+    th0 = np.array([[1.0, 0.6]])
+    T = 1.0
+    exact = 2 * np.arctan(np.tan(0.4 / 2) * np.exp(2 * K * T))
+    errs = []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        steps = int(round(T / dt))
+        out = orc.run_csr(rp, cl, J, th0, q=2, dt=dt, K=np.full(steps, K), Ks=np.zeros(steps),
+                          sigma=np.zeros(steps), seeds=np.zeros(1, np.uint64))
+        d = np.mod(out[0, 0] - out[0, 1], TWO_PI)
+        errs.append(abs(d - exact))
+        # the mean phase does not move
+        m = np.angle(np.exp(1j * out[0]).sum())
+        assert abs(np.mod(m - 0.8 + np.pi, TWO_PI) - np.pi) < 1e-12
+    assert errs[0] < 2e-2
+    assert 1.8 < errs[0] / errs[1] < 2.2 and 1.8 < errs[1] / errs[2] < 2.2
+
+
+@pytest.mark.parametrize("q", [2, 3, 4])
+def test_shil_closed_form(orc, q):
+    # K = sigma = 0: u = q theta obeys u' = -q Ks sin u, tan(u/2) = tan(u0/2) exp(-q Ks t)
+    Ks, T, dt = 1.3, 0.8, 1e-4
+    steps = int(round(T / dt))
+    th0 = np.array([[0.3 / q, 1.0 / q, 2.9 / q]])
+    rp = np.zeros(4, np.int64)
+    out = orc.run_csr(rp, np.zeros(0, np.int32), np.zeros(0), th0, q=q, dt=dt, K=np.zeros(steps),
+                      Ks=np.full(steps, Ks), sigma=np.zeros(steps), seeds=np.zeros(1, np.uint64))
+    u0 = q * th0[0]
+    exact = 2 * np.arctan(np.tan(u0 / 2) * np.exp(-q * Ks * T)) / q
+    assert np.max(np.abs(out[0] - exact)) < 1e-4
+
+
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_shil_fixed_points(orc, q):
+    # stable at 2 pi k / q, unstable at (2k+1) pi / q
+    steps, dt = 4000, 0.01
+    k = np.arange(q)
+    stable = 2 * np.pi * k / q
+    th0 = np.concatenate([stable + 0.2 * np.pi / q, stable - 0.2 * np.pi / q,
+                          stable + np.pi / q + 1e-3])[None, :]
+    n = th0.shape[1]
+    out = orc.run_csr(np.zeros(n + 1, np.int64), np.zeros(0, np.int32), np.zeros(0), th0, q=q,
+                      dt=dt, K=np.zeros(steps), Ks=np.full(steps, 1.0), sigma=np.zeros(steps),
+                      seeds=np.zeros(1, np.uint64))[0]
+    np.testing.assert_allclose(_wrapdiff(out[:2 * q], np.tile(stable, 2)), 0, atol=1e-9)
+    # the points started just past an unstable point fell to the next stable one
+    assert np.max(_wrapdiff(out[2 * q:], np.mod(stable + 2 * np.pi / q, TWO_PI))) < 1e-9
+    # exactly at a stable point nothing moves
+    still = orc.run_csr(np.zeros(q + 1, np.int64), np.zeros(0, np.int32), np.zeros(0),
+                        stable[None, :], q=q, dt=dt, K=np.zeros(10), Ks=np.full(10, 1.0),
+                        sigma=np.zeros(10), seeds=np.zeros(1, np.uint64))[0]
+    assert np.max(_wrapdiff(still, stable)) < 1e-12
+
+
+def test_coupling_conserves_phase_sum(orc):
+    # Ks = 0: the coupling of a symmetric J cancels pairwise, so the sum of
+    # phases moves by the noise alone (mod 2 pi).
+    g = synth.random_small(14, 0.4, seed=8, weights="real")
+    steps, dt = 40, 0.02
+    th0 = synth.theta0(2, 14, seed=3)
+    sig = synth.const(0.2, steps)
+    sd = synth.seeds(2, 9)
+    out = orc.run_csr(g.row_ptr, g.col, -g.w, th0, q=2, dt=dt, K=synth.const(1.5, steps),
+                      Ks=np.zeros(steps), sigma=sig, seeds=sd)
+    for r in range(2):
+        kicks = sum(float(sig[s]) * np.sqrt(dt) * orc.normals(int(sd[r]), 0, 14, s).sum()
+                    for s in range(steps))
+        lhs = out[r].sum() - th0[r].astype(np.float64).sum() - kicks
+        assert abs(np.mod(lhs + np.pi, TWO_PI) - np.pi) < 1e-10
+
+
+def _lyapunov(theta, g, J, K, Ks, q):
+    ei, ej, _ = g.upper_edges()
+    Jup = J[np.repeat(np.arange(g.n), np.diff(g.row_ptr)) < g.col]
+    return (-K * np.sum(Jup * np.cos(theta[ei] - theta[ej]))
+            - Ks / q * np.sum(np.cos(q * theta)))
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_noiseless_flow_descends_energy(orc, q):
+    # sigma = 0, constant K and Ks: Euler steps on dtheta/dt = -grad E with a
+    # small dt never raise E = -K sum J cos(d) - Ks/q sum cos(q theta).
+    g = synth.random_small(16, 0.35, seed=10, weights="pm1")
+    J = -g.w.astype(np.float64)
+    K, Ks, dt = 1.0, 0.7, 0.005
+    th = synth.theta0(1, 16, seed=4).astype(np.float64)
+    E = [_lyapunov(th[0], g, J, K, Ks, q)]
+    for _ in range(200):
+        th = orc.run_csr(g.row_ptr, g.col, J, th, q=q, dt=dt, K=[K], Ks=[Ks], sigma=[0.0],
+                         seeds=np.zeros(1, np.uint64))
+        E.append(_lyapunov(th[0], g, J, K, Ks, q))
+    assert np.all(np.diff(E) <= 1e-12)
+    assert E[-1] < E[0] - 0.5
+
+
+def test_csr_and_dense_agree(orc):
+    g = synth.random_small(12, 0.5, seed=11, weights="real")
+    Jd = np.zeros((12, 12))
+    ei, ej, w = g.upper_edges()
+    Jd[ei, ej] = -w
+    Jd[ej, ei] = -w
+    np.fill_diagonal(Jd, 5.0)  # the diagonal of a dense coupling is ignored
+    steps = 30
+    kw = dict(q=3, dt=0.01, K=synth.ramp(0.1, 2.0, steps), Ks=synth.ramp(0, 3.0, steps),
+              sigma=synth.const(0.1, steps), seeds=synth.seeds(2, 4), step0=3)
+    th0 = synth.theta0(2, 12, seed=5)
+    a = orc.run_csr(g.row_ptr, g.col, -g.w, th0, **kw)
+    b = orc.run_dense(Jd, th0, **kw)
+    assert np.max(_wrapdiff(a, b)) < 1e-12
+
+
+def test_resume_and_replica_independence(orc):
+    g = synth.erdos_renyi(40, 0.2, seed=12)
+    steps = 20
+    K, Ks, sig = synth.ramp(0.1, 1, steps), synth.ramp(0, 2, steps), synth.const(0.1, steps)
+    th0 = synth.theta0(3, 40, seed=6)
+    sd = synth.seeds(3, 100)
+    full = orc.run_csr(g.row_ptr, g.col, -g.w, th0, q=2, dt=0.01, K=K, Ks=Ks, sigma=sig, seeds=sd)
+    half = orc.run_csr(g.row_ptr, g.col, -g.w, th0, q=2, dt=0.01, K=K[:8], Ks=Ks[:8],
+                       sigma=sig[:8], seeds=sd)
+    rest = orc.run_csr(g.row_ptr, g.col, -g.w, half, q=2, dt=0.01, K=K[8:], Ks=Ks[8:],
+                       sigma=sig[8:], seeds=sd, step0=8)
+    np.testing.assert_array_equal(full, rest)
+    one = orc.run_csr(g.row_ptr, g.col, -g.w, th0[1:2], q=2, dt=0.01, K=K, Ks=Ks, sigma=sig,
+                      seeds=sd[1:2])
+    np.testing.assert_array_equal(full[1:2], one)
