@@ -1,0 +1,205 @@
+/*
+ * oim.h -- C ABI of the MI355X simulated oscillator Ising/Potts machine.
+ *
+ * The library integrates the noisy Kuramoto network with sub-harmonic
+ * injection locking of arXiv 2505.22631 (Sec. II-D Eq. 4, Sec. II-E Eq. 5,
+ * Algorithm 1) on a gfx950 GPU and reads the result out as spins/colours,
+ * cut values, colouring conflicts and energies (Sec. II-A Eq. 1 and 2,
+ * Sec. II-E Eq. 6).
+ *
+ * Conventions (every entry point):
+ *   - Phases are radians.  theta is a caller-owned FP32 device array laid out
+ *     [R][n] (replica-major).  The library keeps phases in one period.
+ *   - On the device a phase is a 32-bit fixed-point fraction of a turn,
+ *     u = theta / 2pi * 2^32 mod 2^32 (the "phase word"): the wrap into one
+ *     period is exact and the state resolution is 2^-32 turn.  Runs read and
+ *     write FP32 radians; callers that need the exact state (checkpoints,
+ *     bit-exact resume) also pass the phase words.
+ *   - J is the Ising/Potts coupling of Eq. 1 / Eq. 2 (H = -sum_{i<j} J_ij s_i s_j).
+ *     Max-cut with edge weights w maps to J = -w, graph colouring to J = -1 on
+ *     every edge (Sec. II-C).  J must be symmetric; the diagonal is ignored.
+ *   - The integrated drift, per oscillator i and step t, is
+ *         f_i = -K_t * sum_j J_ij sin(theta_i - theta_j) - Ks_t * sin(q theta_i)
+ *     and the Euler-Maruyama step is
+ *         theta_i <- wrap(theta_i + dt f_i + sigma_t sqrt(dt) xi_{i,t}),
+ *     all oscillators updated from the phases of step t (Algorithm 1).
+ *   - xi_{i,t} for replica r comes from Philox4x32-10 (Salmon et al., SC'11)
+ *     with key (seed_r low word, seed_r high word) and counter (i/4, t, 0, 0),
+ *     t the global step index; words (x0,x1) feed oscillators i%4 = 0,1 and
+ *     (x2,x3) feed i%4 = 2,3 through Box-Muller on 24-bit uniforms
+ *     u1 = ((xa>>8)+1)/2^24, u2 = (xb>>8)/2^24: the even oscillator of a pair
+ *     takes sqrt(-2 ln u1) cos(2 pi u2), the odd one the sine.
+ *   - Device pointers must be on the device that was current when the problem
+ *     was created.  Work is enqueued on `stream` (NULL = the null stream) and
+ *     is asynchronous unless stated otherwise.
+ *   - Every function returns an oim_status and never aborts.  All argument
+ *     checks run on the host before any device work, so a rejected call leaves
+ *     device memory untouched.  oim_last_error() holds a per-thread detail
+ *     string for the last failure.
+ *   - A problem may be used by one stream at a time.
+ */
+#ifndef OIM_H
+#define OIM_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define OIM_ABI_VERSION 1
+
+typedef enum {
+    OIM_OK = 0,
+    OIM_E_ARG = 1,          /* bad argument: NULL pointer, size or range     */
+    OIM_E_CSR = 2,          /* malformed CSR (order, range, loops, repeats)  */
+    OIM_E_ASYM = 3,         /* J is not exactly symmetric                    */
+    OIM_E_NONFINITE = 4,    /* NaN or Inf in J                               */
+    OIM_E_UNSUPPORTED = 5,  /* valid request the library cannot serve        */
+    OIM_E_NOMEM = 6,        /* device or host allocation failed              */
+    OIM_E_HIP = 7,          /* a HIP runtime call failed (see last_error)    */
+    OIM_E_STATE = 8         /* object used after destroy / wrong device      */
+} oim_status;
+
+typedef struct oim_problem_s* oim_problem;
+
+/* Version of this ABI (OIM_ABI_VERSION). */
+int oim_abi_version(void);
+
+/* Static name of a status code ("OIM_E_CSR", ...). */
+const char* oim_status_str(int status);
+
+/* Detail of the last failure on the calling thread ("" if none). */
+const char* oim_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Problem upload (Sec. III-B: the coupling matrix is stored on the device).
+ * Inputs are HOST pointers and are copied; the caller may free them after the
+ * call returns.  The call is synchronous.
+ * ---------------------------------------------------------------------- */
+
+/* Sparse coupling in CSR form: row_ptr[n+1] (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz), col_idx[nnz] strictly increasing within each row, in
+ * [0, n), no diagonal entries; J[nnz] finite and symmetric (the entry (j,i)
+ * exists and has bit-identical value for every stored (i,j)).
+ * Errors: OIM_E_ARG (n < 1, n > 2^24, nnz < 0, NULL pointer), OIM_E_CSR,
+ * OIM_E_ASYM, OIM_E_NONFINITE, OIM_E_NOMEM, OIM_E_HIP.  flags must be 0. */
+int oim_problem_from_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                         const float* J, uint32_t flags, oim_problem* out);
+
+/* Dense coupling J[n][n] row-major (Sec. III-B: flattened coupling matrix).
+ * J must be finite and symmetric off the diagonal; the diagonal is ignored.
+ * Errors as for oim_problem_from_csr.  1 <= n <= 65536.  flags must be 0. */
+int oim_problem_from_dense(int32_t n, const float* J, uint32_t flags, oim_problem* out);
+
+/* Frees every device and host resource of p.  NULL is a no-op.  Waits for the
+ * device work already enqueued on p to finish. */
+void oim_problem_destroy(oim_problem p);
+
+typedef struct {
+    int32_t n;                 /* oscillators                                       */
+    int32_t is_dense;          /* 1 for oim_problem_from_dense                      */
+    int64_t nnz;               /* stored off-diagonal nonzeros (both triangles)     */
+    int32_t integer_weights;   /* 1 if every J is an integer of magnitude < 2^24    */
+    int32_t reserved;
+    double max_abs_row_sum;    /* max_i sum_j |J_ij| (Gershgorin bound of J)         */
+    double sum_J_upper;        /* sum_{i<j} J_ij; max-cut total weight W = -this     */
+} oim_problem_info;
+
+/* Fills *info (host memory).  Synchronous, no device work. */
+int oim_problem_info_get(oim_problem p, oim_problem_info* info);
+
+/* ------------------------------------------------------------------------
+ * Run: steps of Algorithm 1 on R independent replicas.
+ * ---------------------------------------------------------------------- */
+
+/* cfg.flags: loop form and precision (one of each; 0 = AUTO / FP32). */
+#define OIM_LOOP_AUTO        0x0u
+#define OIM_LOOP_PERSISTENT  0x1u  /* one launch, replica state resident in LDS      */
+#define OIM_LOOP_STEPWISE    0x2u  /* one kernel per step, state in device memory    */
+#define OIM_LOOP_MASK        0x3u
+#define OIM_PREC_FP32        0x0u  /* FP32 coupling sum                              */
+#define OIM_PREC_BF16X3      0x10u /* dense only: BF16 three-term split on MFMA       */
+#define OIM_PREC_MASK        0x30u
+
+typedef struct {
+    int32_t q;              /* stable phases per oscillator: 2 = Ising, 3.. = Potts (<= 16) */
+    int32_t R;              /* replicas (independent copies, own seeds), >= 1              */
+    int32_t steps;          /* Euler-Maruyama steps, >= 0                                 */
+    float dt;               /* time step h of Algorithm 1, finite and > 0                  */
+    int32_t readout_every;  /* M > 0: threshold + energy every M steps and after the last  */
+                            /* step; 0: no in-run readout                                  */
+    uint32_t flags;         /* OIM_LOOP_* | OIM_PREC_*                                      */
+} oim_run_cfg;
+
+/* Optional in-run readout buffers (device memory, any may be NULL).
+ * With M = readout_every > 0 there are ceil(steps / M) readouts, after local
+ * steps M, 2M, ... and after the last step.  At each readout every replica's
+ * phases are thresholded to colours k = floor(q * u / 2^32 + 1/2) mod q from
+ * the exact phase words u, and H is evaluated: Eq. 1 (q = 2, spin s = 1 - 2k)
+ * or Eq. 2 (q >= 3).
+ *   trace[ceil(steps/M)][R]  H at every readout
+ *   best_h[R]                lowest H seen in this call (first occurrence)
+ *   best_step[R]             global step index after which best_h was seen
+ *   best_colour[R][n]        colours at that readout                           */
+typedef struct {
+    double* trace;
+    double* best_h;
+    int32_t* best_step;
+    int8_t* best_colour;
+} oim_readout;
+
+/* K, Ks, sigma: device FP32 [steps], indexed by the LOCAL step s = 0..steps-1
+ * (coupling strength, SHIL strength, noise amplitude per step).
+ * seeds: device uint64 [R].  step0: global index of the first step (noise
+ * counter).  theta: device FP32 [R][n], overwritten with the final phases in
+ * [0, 2pi).  phase: NULL, or device uint32 [R][n] phase words; when given,
+ * the initial state is read from phase (theta's input is ignored) and the
+ * final state is written to both.  Resuming with the phase words of a
+ * previous call, step0 = its end and the schedule suffix reproduces an
+ * uninterrupted run bit for bit.  steps = 0 does no device work.
+ * readout may be NULL.  Errors: OIM_E_ARG, OIM_E_UNSUPPORTED (e.g. BF16X3 on
+ * a sparse problem, PERSISTENT when a replica does not fit in LDS),
+ * OIM_E_NOMEM, OIM_E_HIP. */
+int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+            const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+            uint32_t* phase, const oim_readout* readout, hipStream_t stream);
+
+/* Phase words <-> radians for count elements (device arrays):
+ * phase = rint(frac(theta / 2pi) * 2^32) mod 2^32 (FP64), and
+ * theta = nearest FP32 to phase * 2pi / 2^32, kept below 2pi.
+ * Non-finite theta gives phase 0. */
+int oim_phase_from_theta(int64_t count, const float* theta, uint32_t* phase, hipStream_t stream);
+int oim_theta_from_phase(int64_t count, const uint32_t* phase, float* theta, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Readout (Sec. III-B phase threshold kernel; Eq. 1, 2, 6).
+ * ---------------------------------------------------------------------- */
+
+/* colour[k] = floor(fmaf(theta[k], (float)(q / 2pi), 0.5f)) mod q for
+ * count elements (FP32 decision), -1 where theta is NaN, Inf or
+ * |theta| >= 2^20.  Device arrays; 2 <= q <= 16; count >= 0. */
+int oim_round(int32_t q, int64_t count, const float* theta, int8_t* colour, hipStream_t stream);
+
+/* Max-cut value per replica: cut[r] = sum_{i<j} (-J_ij) [colour_ri != colour_rj]
+ * over colour[R][n].  cut_i64 (exact) requires integer_weights; cut_f64 is the
+ * same sum in FP64 (exact for integer weights).  Either may be NULL. */
+int oim_cut(oim_problem p, int32_t R, const int8_t* colour, int64_t* cut_i64, double* cut_f64,
+            hipStream_t stream);
+
+/* Colouring conflicts per replica: #{i<j : J_ij != 0, colour_ri == colour_rj}. */
+int oim_conflicts(oim_problem p, int32_t R, const int8_t* colour, int64_t* conflicts,
+                  hipStream_t stream);
+
+/* Energies per replica, FP64: h_model[r] = Eq. 1 (q = 2) or Eq. 2 (q >= 3) at
+ * colour[R][n]; h_eq6[r] = sum_{i<j} (-J_ij) cos(theta_ri - theta_rj), Eq. 6
+ * with the edge weights w = -J, at the continuous phases theta[R][n].
+ * Either output may be NULL (then its input may be NULL too). */
+int oim_energy(oim_problem p, int32_t q, int32_t R, const float* theta, const int8_t* colour,
+               double* h_model, double* h_eq6, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OIM_H */

@@ -1,0 +1,306 @@
+// api.cpp -- the extern "C" entry points of include/oim.h.
+// Host-side validation always runs before the first HIP call of an entry
+// point; device memory of a problem is owned by its oim_problem handle.
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace oim {
+const char* last_error_cstr();
+}  // namespace oim
+
+using namespace oim;
+
+namespace {
+
+template <typename T>
+int dev_upload(T** dst, const T* src, size_t count, const char* what) {
+    *dst = nullptr;
+    if (count == 0) return OIM_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        if (e == hipErrorOutOfMemory) return set_error(OIM_E_NOMEM, std::string(what) + ": out of device memory");
+        return hip_error(e, what);
+    }
+    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_error(e, what);
+    return OIM_OK;
+}
+
+void release(Problem* p) {
+    if (!p) return;
+    hipFree(p->d_row_ptr);
+    hipFree(p->d_col);
+    hipFree(p->d_J);
+    hipFree(p->d_sell_desc);
+    hipFree(p->d_sell);
+    hipFree(p->d_work);
+    dense_release(p);
+    p->magic = kDeadMagic;
+    delete p;
+}
+
+void weight_stats(Problem* p, int32_t n, const int64_t* row_ptr, const int32_t* col,
+                  const float* J) {
+    bool integer = true;
+    double mx = 0.0, upper = 0.0;
+    for (int32_t i = 0; i < n; ++i) {
+        double row = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const double w = J[e];
+            row += std::fabs(w);
+            if (col[e] > i) upper += w;
+            if (w != std::nearbyint(w) || std::fabs(w) >= 16777216.0) integer = false;
+        }
+        if (row > mx) mx = row;
+    }
+    p->integer_weights = integer;
+    p->max_abs_row_sum = mx;
+    p->sum_J_upper = upper;
+}
+
+int current_device(int* dev) {
+    const hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
+    return OIM_OK;
+}
+
+int check_device(const Problem* p) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return set_error(OIM_E_STATE, "problem belongs to another device");
+    return OIM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+__attribute__((visibility("default"))) int oim_abi_version(void) { return OIM_ABI_VERSION; }
+
+__attribute__((visibility("default"))) const char* oim_status_str(int s) {
+    switch (s) {
+        case OIM_OK: return "OIM_OK";
+        case OIM_E_ARG: return "OIM_E_ARG";
+        case OIM_E_CSR: return "OIM_E_CSR";
+        case OIM_E_ASYM: return "OIM_E_ASYM";
+        case OIM_E_NONFINITE: return "OIM_E_NONFINITE";
+        case OIM_E_UNSUPPORTED: return "OIM_E_UNSUPPORTED";
+        case OIM_E_NOMEM: return "OIM_E_NOMEM";
+        case OIM_E_HIP: return "OIM_E_HIP";
+        case OIM_E_STATE: return "OIM_E_STATE";
+        default: return "OIM_E_UNKNOWN";
+    }
+}
+
+__attribute__((visibility("default"))) const char* oim_last_error(void) {
+    return last_error_cstr();
+}
+
+__attribute__((visibility("default"))) int oim_problem_from_csr(
+    int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+    uint32_t flags, oim_problem* out) {
+    clear_error();
+    if (!out) return set_error(OIM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags != 0) return set_error(OIM_E_ARG, "flags must be 0");
+    int st = validate_csr(n, nnz, row_ptr, col_idx, J);
+    if (st) return st;
+    Problem* p = new (std::nothrow) Problem();
+    if (!p) return set_error(OIM_E_NOMEM, "host allocation failed");
+    p->n = n;
+    p->nnz = nnz;
+    weight_stats(p, n, row_ptr, col_idx, J);
+    SellImage img;
+    build_sell(n, row_ptr, col_idx, J, img);
+    p->sell_slices = img.slices;
+    p->sell_entries = (int64_t)img.entries.size();
+    if ((st = current_device(&p->device)) ||
+        (st = dev_upload(&p->d_row_ptr, row_ptr, (size_t)n + 1, "upload row_ptr")) ||
+        (st = dev_upload(&p->d_col, col_idx, (size_t)nnz, "upload col_idx")) ||
+        (st = dev_upload(&p->d_J, J, (size_t)nnz, "upload J")) ||
+        (st = dev_upload(&p->d_sell_desc, img.desc.data(), img.desc.size(), "upload slices")) ||
+        (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell"))) {
+        release(p);
+        return st;
+    }
+    *out = reinterpret_cast<oim_problem>(p);
+    return OIM_OK;
+}
+
+__attribute__((visibility("default"))) int oim_problem_from_dense(int32_t n, const float* J,
+                                                                  uint32_t flags,
+                                                                  oim_problem* out) {
+    clear_error();
+    if (!out) return set_error(OIM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags != 0) return set_error(OIM_E_ARG, "flags must be 0");
+    int st = validate_dense(n, J);
+    if (st) return st;
+    Problem* p = new (std::nothrow) Problem();
+    if (!p) return set_error(OIM_E_NOMEM, "host allocation failed");
+    p->n = n;
+    p->dense = true;
+    // statistics over the off-diagonal entries
+    bool integer = true;
+    double mx = 0.0, upper = 0.0;
+    int64_t nz = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        double row = 0.0;
+        for (int32_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double w = J[(int64_t)i * n + j];
+            if (w != 0.0) ++nz;
+            row += std::fabs(w);
+            if (j > i) upper += w;
+            if (w != std::nearbyint(w) || std::fabs(w) >= 16777216.0) integer = false;
+        }
+        if (row > mx) mx = row;
+    }
+    p->nnz = nz;
+    p->integer_weights = integer;
+    p->max_abs_row_sum = mx;
+    p->sum_J_upper = upper;
+    if ((st = current_device(&p->device)) || (st = dense_prepare(p, J))) {
+        release(p);
+        return st;
+    }
+    *out = reinterpret_cast<oim_problem>(p);
+    return OIM_OK;
+}
+
+__attribute__((visibility("default"))) void oim_problem_destroy(oim_problem h) {
+    Problem* p = checked(h);
+    if (!p) return;
+    hipDeviceSynchronize();
+    release(p);
+}
+
+__attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
+                                                                oim_problem_info* info) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (!info) return set_error(OIM_E_ARG, "info is NULL");
+    std::memset(info, 0, sizeof *info);
+    info->n = p->n;
+    info->is_dense = p->dense ? 1 : 0;
+    info->nnz = p->nnz;
+    info->integer_weights = p->integer_weights ? 1 : 0;
+    info->max_abs_row_sum = p->max_abs_row_sum;
+    info->sum_J_upper = p->sum_J_upper;
+    return OIM_OK;
+}
+
+__attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_cfg* cfg,
+                                                   const float* K, const float* Ks,
+                                                   const float* sigma, const uint64_t* seeds,
+                                                   int64_t step0, float* theta, uint32_t* phase,
+                                                   const oim_readout* ro, hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    int st = validate_cfg(p, cfg);
+    if (st) return st;
+    if (!theta || !seeds) return set_error(OIM_E_ARG, "theta or seeds is NULL");
+    if (cfg->steps > 0 && (!K || !Ks || !sigma))
+        return set_error(OIM_E_ARG, "schedule pointer is NULL");
+    if (step0 < 0 || step0 + (int64_t)cfg->steps > ((int64_t)1 << 32))
+        return set_error(OIM_E_ARG, "global step index must stay below 2^32");
+    if (ro && cfg->readout_every == 0 && (ro->trace || ro->best_h || ro->best_step || ro->best_colour))
+        return set_error(OIM_E_ARG, "readout buffers given with readout_every = 0");
+    if ((st = check_device(p))) return st;
+    if (cfg->steps == 0) return OIM_OK;  // nothing to integrate; theta untouched
+    const uint32_t loop = cfg->flags & OIM_LOOP_MASK;
+    if (p->dense) {
+        if (loop == OIM_LOOP_PERSISTENT)
+            return set_error(OIM_E_UNSUPPORTED, "dense problems run stepwise");
+        return launch_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
+    }
+    const bool fits = persistent_sparse_fits(p);
+    if (loop == OIM_LOOP_PERSISTENT || (loop == OIM_LOOP_AUTO && fits))
+        return launch_persistent_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro,
+                                        stream);
+    return launch_stepwise_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
+}
+
+__attribute__((visibility("default"))) int oim_phase_from_theta(int64_t count,
+                                                                const float* theta,
+                                                                uint32_t* phase,
+                                                                hipStream_t stream) {
+    clear_error();
+    if (count < 0) return set_error(OIM_E_ARG, "count must be >= 0");
+    if (count > 0 && (!theta || !phase)) return set_error(OIM_E_ARG, "NULL array");
+    return launch_phase_convert(count, theta, phase, nullptr, nullptr, stream);
+}
+
+__attribute__((visibility("default"))) int oim_theta_from_phase(int64_t count,
+                                                                const uint32_t* phase,
+                                                                float* theta,
+                                                                hipStream_t stream) {
+    clear_error();
+    if (count < 0) return set_error(OIM_E_ARG, "count must be >= 0");
+    if (count > 0 && (!theta || !phase)) return set_error(OIM_E_ARG, "NULL array");
+    return launch_phase_convert(count, nullptr, nullptr, phase, theta, stream);
+}
+
+__attribute__((visibility("default"))) int oim_round(int32_t q, int64_t count, const float* theta,
+                                                     int8_t* colour, hipStream_t stream) {
+    clear_error();
+    if (q < 2 || q > kMaxQ) return set_error(OIM_E_ARG, "q must be in [2, 16]");
+    if (count < 0) return set_error(OIM_E_ARG, "count must be >= 0");
+    if (count > 0 && (!theta || !colour)) return set_error(OIM_E_ARG, "NULL array");
+    return launch_round(q, count, theta, colour, stream);
+}
+
+__attribute__((visibility("default"))) int oim_cut(oim_problem h, int32_t R, const int8_t* colour,
+                                                   int64_t* cut_i64, double* cut_f64,
+                                                   hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (R < 1) return set_error(OIM_E_ARG, "R must be >= 1");
+    if (!colour) return set_error(OIM_E_ARG, "colour is NULL");
+    if (cut_i64 && !p->integer_weights)
+        return set_error(OIM_E_UNSUPPORTED, "exact int64 cut needs integer weights");
+    if (!cut_i64 && !cut_f64) return OIM_OK;
+    int st = check_device(p);
+    if (st) return st;
+    return launch_cut(p, R, colour, cut_i64, cut_f64, stream);
+}
+
+__attribute__((visibility("default"))) int oim_conflicts(oim_problem h, int32_t R,
+                                                         const int8_t* colour, int64_t* conflicts,
+                                                         hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (R < 1) return set_error(OIM_E_ARG, "R must be >= 1");
+    if (!colour || !conflicts) return set_error(OIM_E_ARG, "NULL array");
+    int st = check_device(p);
+    if (st) return st;
+    return launch_conflicts(p, R, colour, conflicts, stream);
+}
+
+__attribute__((visibility("default"))) int oim_energy(oim_problem h, int32_t q, int32_t R,
+                                                      const float* theta, const int8_t* colour,
+                                                      double* h_model, double* h_eq6,
+                                                      hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (q < 2 || q > kMaxQ) return set_error(OIM_E_ARG, "q must be in [2, 16]");
+    if (R < 1) return set_error(OIM_E_ARG, "R must be >= 1");
+    if (h_model && !colour) return set_error(OIM_E_ARG, "colour is NULL");
+    if (h_eq6 && !theta) return set_error(OIM_E_ARG, "theta is NULL");
+    if (!h_model && !h_eq6) return OIM_OK;
+    int st = check_device(p);
+    if (st) return st;
+    return launch_energy(p, q, R, theta, colour, h_model, h_eq6, stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,102 @@
+// internal.hpp -- host-side structures shared by the library's translation
+// units (not part of the public ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "oim.h"
+
+namespace oim {
+
+constexpr uint32_t kProblemMagic = 0x4f494d50u;  // "OIMP"
+constexpr uint32_t kDeadMagic = 0xdeadbeefu;
+constexpr int kMaxQ = 16;
+constexpr int kSliceQuads = 64;  // quads (4 oscillators) per slice = one wave's lanes
+
+// Sliced-ELL image of a symmetric CSR, laid out for the LDS-resident kernels:
+// slice s covers quads 64s..64s+63 (oscillators 4*quad + j, j = 0..3).  For
+// each (s, j) the rows 4*(64s+l)+j, l = 0..63, are padded to their longest
+// row; entry e of lane l sits at (off[s][j] + e) * 64 + l and holds the LDS
+// byte offset of the neighbour's (sin, cos) pair and the bits of J.  Padding
+// entries carry J = 0 and point at a valid row.  Oscillator i lives at LDS
+// slot (i % 4) * (64 * slices) + i / 4 (four planes, one per quad member).
+struct SellImage {
+    int32_t slices = 0;
+    std::vector<int32_t> desc;   // [slices][8]: off[4], deg[4]
+    std::vector<int2> entries;   // [sum deg * 64]
+};
+
+struct Problem {
+    uint32_t magic = kProblemMagic;
+    int device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    bool dense = false;
+    bool integer_weights = false;
+    double max_abs_row_sum = 0.0;
+    double sum_J_upper = 0.0;
+
+    // device: original CSR (sparse problems), for the readouts
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col = nullptr;
+    float* d_J = nullptr;
+
+    // device: sliced-ELL image for the LDS-resident step kernel
+    int32_t sell_slices = 0;
+    int64_t sell_entries = 0;
+    int32_t* d_sell_desc = nullptr;
+    int2* d_sell = nullptr;
+
+    // device: dense coupling (dense problems), FP32 and the BF16 split
+    float* d_Jdense = nullptr;
+    uint16_t* d_Jhi = nullptr;
+    uint16_t* d_Jlo = nullptr;
+
+    // cached workspace for the stepwise / dense loops
+    void* d_work = nullptr;
+    size_t work_bytes = 0;
+};
+
+// error plumbing (errors.cpp)
+int set_error(int status, const std::string& msg);
+int hip_error(hipError_t e, const char* what);
+void clear_error();
+
+// validation helpers (validate.cpp): host only, no HIP calls
+int validate_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                 const float* J);
+int validate_dense(int32_t n, const float* J);
+int validate_cfg(const Problem* p, const oim_run_cfg* cfg);
+Problem* checked(oim_problem p);
+void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+                SellImage& out);
+
+// kernels' host launchers
+int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,
+                             const float* Ks, const float* sigma, const uint64_t* seeds,
+                             int64_t step0, float* theta, uint32_t* phase,
+                             const oim_readout* ro, hipStream_t stream);
+int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                           const float* sigma, const uint64_t* seeds, int64_t step0,
+                           float* theta, uint32_t* phase, const oim_readout* ro,
+                           hipStream_t stream);
+int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                 const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                 uint32_t* phase, const oim_readout* ro, hipStream_t stream);
+int dense_prepare(Problem* p, const float* J);
+void dense_release(Problem* p);
+int launch_phase_convert(int64_t count, const float* theta_in, uint32_t* phase_out,
+                         const uint32_t* phase_in, float* theta_out, hipStream_t s);
+bool persistent_sparse_fits(const Problem* p);
+int launch_round(int32_t q, int64_t count, const float* theta, int8_t* colour, hipStream_t s);
+int launch_cut(const Problem* p, int32_t R, const int8_t* colour, int64_t* cut_i64,
+               double* cut_f64, hipStream_t s);
+int launch_conflicts(const Problem* p, int32_t R, const int8_t* colour, int64_t* conflicts,
+                     hipStream_t s);
+int launch_energy(const Problem* p, int32_t q, int32_t R, const float* theta,
+                  const int8_t* colour, double* h_model, double* h_eq6, hipStream_t s);
+
+}  // namespace oim

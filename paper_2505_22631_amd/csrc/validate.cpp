@@ -1,0 +1,171 @@
+// validate.cpp -- host-only argument checks and the sliced-ELL builder.
+// Nothing here touches the HIP runtime, so every rejection path can be
+// exercised on a machine without a GPU.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <string>
+
+#include "internal.hpp"
+
+namespace oim {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const std::string& msg) {
+    g_last_error = msg;
+    return status;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+int hip_error(hipError_t e, const char* what) {
+    return set_error(OIM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+const char* last_error_cstr() { return g_last_error.c_str(); }
+
+static uint32_t bits(float x) {
+    uint32_t u;
+    std::memcpy(&u, &x, 4);
+    return u;
+}
+
+int validate_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
+                 const float* J) {
+    if (n < 1 || n > (1 << 24)) return set_error(OIM_E_ARG, "n must be in [1, 2^24]");
+    if (nnz < 0) return set_error(OIM_E_ARG, "nnz must be >= 0");
+    if (!row_ptr) return set_error(OIM_E_ARG, "row_ptr is NULL");
+    if (nnz > 0 && (!col_idx || !J)) return set_error(OIM_E_ARG, "col_idx or J is NULL");
+    if (row_ptr[0] != 0) return set_error(OIM_E_CSR, "row_ptr[0] != 0");
+    if (row_ptr[n] != nnz) return set_error(OIM_E_CSR, "row_ptr[n] != nnz");
+    for (int32_t i = 0; i < n; ++i) {
+        if (row_ptr[i + 1] < row_ptr[i])
+            return set_error(OIM_E_CSR, "row_ptr decreases at row " + std::to_string(i));
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col_idx[e];
+            if (j < 0 || j >= n)
+                return set_error(OIM_E_CSR, "column out of range in row " + std::to_string(i));
+            if (j == i)
+                return set_error(OIM_E_CSR, "diagonal entry in row " + std::to_string(i));
+            if (e > row_ptr[i] && col_idx[e - 1] >= j)
+                return set_error(OIM_E_CSR,
+                                 "columns not strictly increasing in row " + std::to_string(i));
+        }
+    }
+    for (int64_t e = 0; e < nnz; ++e)
+        if (!std::isfinite(J[e])) return set_error(OIM_E_NONFINITE, "non-finite J entry");
+    // symmetry: (j, i) exists with the same bits for every stored (i, j)
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col_idx[e];
+            const int32_t* b = col_idx + row_ptr[j];
+            const int32_t* en = col_idx + row_ptr[j + 1];
+            const int32_t* hit = std::lower_bound(b, en, i);
+            if (hit == en || *hit != i)
+                return set_error(OIM_E_ASYM, "entry (" + std::to_string(i) + "," +
+                                                 std::to_string(j) + ") has no transpose");
+            if (bits(J[hit - col_idx]) != bits(J[e]))
+                return set_error(OIM_E_ASYM, "J(" + std::to_string(i) + "," + std::to_string(j) +
+                                                 ") != J(" + std::to_string(j) + "," +
+                                                 std::to_string(i) + ")");
+        }
+    }
+    return OIM_OK;
+}
+
+int validate_dense(int32_t n, const float* J) {
+    if (n < 1 || n > 65536) return set_error(OIM_E_ARG, "dense n must be in [1, 65536]");
+    if (!J) return set_error(OIM_E_ARG, "J is NULL");
+    const int64_t nn = (int64_t)n * n;
+    for (int64_t k = 0; k < nn; ++k) {
+        if ((k / n) == (k % n)) continue;  // diagonal ignored
+        if (!std::isfinite(J[k])) return set_error(OIM_E_NONFINITE, "non-finite J entry");
+    }
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = i + 1; j < n; ++j)
+            if (bits(J[(int64_t)i * n + j]) != bits(J[(int64_t)j * n + i]))
+                return set_error(OIM_E_ASYM, "J(" + std::to_string(i) + "," + std::to_string(j) +
+                                                 ") != J(" + std::to_string(j) + "," +
+                                                 std::to_string(i) + ")");
+    return OIM_OK;
+}
+
+Problem* checked(oim_problem p) {
+    Problem* pr = reinterpret_cast<Problem*>(p);
+    if (!pr || pr->magic != kProblemMagic) return nullptr;
+    return pr;
+}
+
+int validate_cfg(const Problem* p, const oim_run_cfg* cfg) {
+    if (!cfg) return set_error(OIM_E_ARG, "cfg is NULL");
+    if (cfg->q < 2 || cfg->q > kMaxQ) return set_error(OIM_E_ARG, "q must be in [2, 16]");
+    if (cfg->R < 1) return set_error(OIM_E_ARG, "R must be >= 1");
+    if (cfg->steps < 0) return set_error(OIM_E_ARG, "steps must be >= 0");
+    if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt))
+        return set_error(OIM_E_ARG, "dt must be finite and > 0");
+    if (cfg->readout_every < 0) return set_error(OIM_E_ARG, "readout_every must be >= 0");
+    const uint32_t known = OIM_LOOP_MASK | OIM_PREC_MASK;
+    if (cfg->flags & ~known) return set_error(OIM_E_ARG, "unknown flag bits");
+    const uint32_t loop = cfg->flags & OIM_LOOP_MASK;
+    const uint32_t prec = cfg->flags & OIM_PREC_MASK;
+    if (loop == OIM_LOOP_MASK) return set_error(OIM_E_ARG, "two loop forms requested");
+    if (prec != OIM_PREC_FP32 && prec != OIM_PREC_BF16X3)
+        return set_error(OIM_E_ARG, "unknown precision");
+    if (prec == OIM_PREC_BF16X3 && !p->dense)
+        return set_error(OIM_E_UNSUPPORTED, "BF16X3 applies to dense problems only");
+    if ((int64_t)cfg->R * p->n > ((int64_t)1 << 40))
+        return set_error(OIM_E_ARG, "R * n too large");
+    return OIM_OK;
+}
+
+void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+                SellImage& out) {
+    const int32_t quads = (n + 3) / 4;
+    const int32_t S = (quads + kSliceQuads - 1) / kSliceQuads;
+    out.slices = S;
+    out.desc.assign((size_t)S * 8, 0);
+    int64_t off = 0;
+    for (int32_t s = 0; s < S; ++s) {
+        for (int j = 0; j < 4; ++j) {
+            int32_t mx = 0;
+            for (int l = 0; l < kSliceQuads; ++l) {
+                const int64_t i = 4LL * (s * kSliceQuads + l) + j;
+                if (i < n) mx = std::max<int32_t>(mx, (int32_t)(row_ptr[i + 1] - row_ptr[i]));
+            }
+            out.desc[s * 8 + j] = (int32_t)off;
+            out.desc[s * 8 + 4 + j] = mx;
+            off += mx;
+        }
+    }
+    // LDS position of oscillator i: plane (i % 4) of length S*64, slot i / 4,
+    // so the 64 lanes of a wave touch 64 consecutive (sin, cos) pairs.
+    const int64_t plane = (int64_t)S * kSliceQuads;
+    auto lds_off = [plane](int64_t i) { return (int32_t)(8 * ((i & 3) * plane + (i >> 2))); };
+    out.entries.assign((size_t)off * kSliceQuads, int2{0, 0});
+    for (int32_t s = 0; s < S; ++s) {
+        for (int j = 0; j < 4; ++j) {
+            const int32_t base = out.desc[s * 8 + j], deg = out.desc[s * 8 + 4 + j];
+            for (int l = 0; l < kSliceQuads; ++l) {
+                const int64_t i = 4LL * (s * kSliceQuads + l) + j;
+                const int32_t self = (int32_t)std::min<int64_t>(i, n - 1);
+                const int64_t rb = i < n ? row_ptr[i] : 0;
+                const int64_t rl = i < n ? row_ptr[i + 1] - row_ptr[i] : 0;
+                for (int32_t e = 0; e < deg; ++e) {
+                    int2 v;
+                    if (e < rl) {
+                        v.x = lds_off(col_idx[rb + e]);
+                        float w = J[rb + e];
+                        std::memcpy(&v.y, &w, 4);
+                    } else {
+                        v.x = lds_off(self);
+                        v.y = 0;
+                    }
+                    out.entries[(size_t)(base + e) * kSliceQuads + l] = v;
+                }
+            }
+        }
+    }
+}
+
+}  // namespace oim

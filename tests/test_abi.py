@@ -1,0 +1,126 @@
+"""The C-ABI library loads, exports every symbol include/oim.h declares, and
+rejects bad arguments on the host before any device work (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_symbols():
+    text = open(os.path.join(ROOT, "include", "oim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(oim_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def oim():
+    import paper_2505_22631_amd as m
+    m.lib()
+    return m
+
+
+def test_every_declared_symbol_is_exported(oim):
+    from paper_2505_22631_amd import _lib
+    syms = _header_symbols()
+    assert len(syms) >= 12
+    L = _lib.lib()
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) == set(_lib.PROTOTYPES), "binding prototypes and header disagree"
+
+
+def test_abi_version_and_status_names(oim):
+    from paper_2505_22631_amd import _lib
+    assert oim.oim_abi_version() == 1
+    assert _lib.status_name(0) == "OIM_OK"
+    assert _lib.status_name(3) == "OIM_E_ASYM"
+    assert _lib.status_name(99) == "OIM_E_UNKNOWN"
+
+
+def _csr_call(oim, n, rp, ci, J):
+    L = oim.lib()
+    h = ctypes.c_void_p()
+    rp = np.ascontiguousarray(rp, np.int64)
+    ci = np.ascontiguousarray(ci, np.int32)
+    J = np.ascontiguousarray(J, np.float32)
+    st = L.oim_problem_from_csr(n, ci.size, rp.ctypes.data_as(ctypes.c_void_p),
+                                ci.ctypes.data_as(ctypes.c_void_p),
+                                J.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(h))
+    return st, L.oim_last_error().decode()
+
+
+def test_csr_validation_errors(oim):
+    g = synth.erdos_renyi(30, 0.3, seed=1)
+    rp, ci, J = g.row_ptr.copy(), g.col.copy(), (-g.w).copy()
+    # bad sizes
+    assert _csr_call(oim, 0, [0], [], [])[0] == 1
+    # row_ptr[0] != 0
+    bad = rp.copy(); bad[0] = 1
+    assert _csr_call(oim, 30, bad, ci, J)[0] == 2
+    # unsorted row
+    c2 = ci.copy(); s, e = rp[0], rp[1]; c2[s:e] = c2[s:e][::-1]
+    assert _csr_call(oim, 30, rp, c2, J)[0] == 2
+    # out of range column
+    c3 = ci.copy(); c3[-1] = 30
+    assert _csr_call(oim, 30, rp, c3, J)[0] == 2
+    # self loop
+    tiny_rp, tiny_ci = [0, 1, 2], [0, 0]
+    assert _csr_call(oim, 2, tiny_rp, tiny_ci, [1.0, 1.0])[0] == 2
+    # asymmetric value
+    J2 = J.copy(); J2[0] = 5.0
+    st, msg = _csr_call(oim, 30, rp, ci, J2)
+    assert st == 3 and "!=" in msg
+    # missing transpose
+    assert _csr_call(oim, 3, [0, 1, 1, 1], [1], [1.0])[0] == 3
+    # non-finite
+    J3 = J.copy(); J3[0] = np.nan
+    assert _csr_call(oim, 30, rp, ci, J3)[0] == 4
+
+
+def test_dense_validation_errors(oim):
+    L = oim.lib()
+    h = ctypes.c_void_p()
+    A = np.zeros((4, 4), np.float32)
+    A[0, 1] = 1.0
+    st = L.oim_problem_from_dense(4, A.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(h))
+    assert st == 3
+    A[1, 0] = 1.0
+    A[2, 3] = A[3, 2] = np.inf
+    st = L.oim_problem_from_dense(4, A.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(h))
+    assert st == 4
+    st = L.oim_problem_from_dense(0, A.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(h))
+    assert st == 1
+
+
+def test_invalid_handles_and_args(oim):
+    from paper_2505_22631_amd import _lib
+    L = oim.lib()
+    cfg = _lib.RunCfg(2, 1, 1, 0.01, 0, 0)
+    assert L.oim_run(None, ctypes.byref(cfg), None, None, None, None, 0, None, None, None,
+                     None) == 8
+    assert L.oim_phase_from_theta(-1, None, None, None) == 1
+    assert L.oim_theta_from_phase(3, None, None, None) == 1
+    assert L.oim_round(1, 10, None, None, None) == 1
+    assert L.oim_round(2, -1, None, None, None) == 1
+    assert L.oim_round(2, 0, None, None, None) == 0
+    assert L.oim_cut(None, 1, None, None, None, None) == 8
+    assert L.oim_conflicts(None, 1, None, None, None) == 8
+    assert L.oim_energy(None, 2, 1, None, None, None, None, None) == 8
+    info = _lib.ProblemInfo()
+    assert L.oim_problem_info_get(None, ctypes.byref(info)) == 8
+    L.oim_problem_destroy(None)  # no-op
+
+
+def test_valid_problem_without_gpu_reports_hip_error(oim):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    g = synth.cycle(8)
+    st, msg = _csr_call(oim, 8, g.row_ptr, g.col, -g.w)
+    assert st == 7 and msg
