@@ -16,17 +16,20 @@ constexpr uint32_t kDeadMagic = 0xdeadbeefu;
 constexpr int kMaxQ = 16;
 constexpr int kSliceQuads = 64;  // quads (4 oscillators) per slice = one wave's lanes
 
-// Sliced-ELL image of a symmetric CSR, laid out for the LDS-resident kernels:
-// slice s covers quads 64s..64s+63 (oscillators 4*quad + j, j = 0..3).  For
-// each (s, j) the rows 4*(64s+l)+j, l = 0..63, are padded to their longest
-// row; entry e of lane l sits at (off[s][j] + e) * 64 + l and holds the LDS
-// byte offset of the neighbour's (sin, cos) pair and the bits of J.  Padding
-// entries carry J = 0 and point at a valid row.  Oscillator i lives at LDS
-// slot (i % 4) * (64 * slices) + i / 4 (four planes, one per quad member).
+// Sliced-ELL image of a symmetric CSR, laid out for the LDS-resident kernel:
+// slice s covers quads 64s..64s+63 (oscillators 4*quad + j, j = 0..3).  All
+// 256 rows of a slice are padded to one degree deg_s (a multiple of 4).  Entry
+// e of row j of lane l is the int2 (LDS byte offset of the neighbour's
+// (sin, cos) pair, bits of J); entries e and e+1 (e even) of a lane are
+// adjacent so one 16-byte load fetches both:
+//   int4 index = (base_s + j * deg_s / 2 + e / 2) * 64 + l,  half = e % 2.
+// Padding entries carry J = 0 and point at a valid row.  Oscillator i lives
+// at LDS slot (i % 4) * (64 * slices) + i / 4 (four planes, one per quad
+// member) so the lanes of a wave touch consecutive (sin, cos) pairs.
 struct SellImage {
     int32_t slices = 0;
-    std::vector<int32_t> desc;   // [slices][8]: off[4], deg[4]
-    std::vector<int2> entries;   // [sum deg * 64]
+    std::vector<int2> desc;      // [slices]: (base_s in int4 rows, deg_s)
+    std::vector<int2> entries;   // [sum_s 4 * deg_s * 64]
 };
 
 struct Problem {
@@ -47,7 +50,7 @@ struct Problem {
     // device: sliced-ELL image for the LDS-resident step kernel
     int32_t sell_slices = 0;
     int64_t sell_entries = 0;
-    int32_t* d_sell_desc = nullptr;
+    int2* d_sell_desc = nullptr;
     int2* d_sell = nullptr;
 
     // device: dense coupling (dense problems), FP32 and the BF16 split

@@ -33,34 +33,43 @@ namespace oim {
 namespace {
 
 struct PersistArgs {
-    const int2* sell;
-    const int32_t* desc;
-    int32_t S;        // slices
-    int32_t plane;    // S * 64: length of one LDS plane
+    const int4* sell;   // sliced-ELL entries, two per int4 (see SellImage)
+    const int2* desc;   // per slice: (base in int4 rows, padded degree)
+    uint32_t sell_bytes;
+    int32_t S;          // slices
+    int32_t plane;      // S * 64: length of one LDS plane
     int32_t n;
     int32_t q;
     int32_t steps;
-    int32_t M;        // readout period (0 = none)
+    int32_t M;          // readout period (0 = none)
     int64_t step0;
     float dt;
     const float* K;
     const float* Ks;
     const float* sigma;
     const uint64_t* seeds;
-    float* theta;     // [R][n]
-    uint32_t* phase;  // [R][n] or null
-    double* trace;    // [ceil(steps/M)][R]
-    double* best_h;   // [R]
+    float* theta;       // [R][n]
+    uint32_t* phase;    // [R][n] or null
+    double* trace;      // [ceil(steps/M)][R]
+    double* best_h;     // [R]
     int32_t* best_step;
     int8_t* best_colour;  // [R][n]
     int32_t R;
 };
 
+__device__ __forceinline__ int4 load_pair(__amdgpu_buffer_rsrc_t rsrc, int voff, int soff) {
+    return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0));
+}
+
+__device__ __forceinline__ float2 sc_at(const unsigned char* smem, int byte_off) {
+    return *reinterpret_cast<const float2*>(smem + byte_off);
+}
+
 template <int TB, int MS, int QM>
 __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     float2* sc = reinterpret_cast<float2*>(smem);                   // [4 * plane]
-    unsigned char* col8 = smem + (size_t)8 * 4 * a.plane;          // [4 * plane]
+    unsigned char* col8 = smem + (size_t)8 * 4 * a.plane;          // [4 * plane] (readout)
     double* red = reinterpret_cast<double*>(col8 + ((4 * a.plane + 15) & ~15));  // [W]
     int* flag = reinterpret_cast<int*>(red + TB / 64);
 
@@ -74,13 +83,20 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
     float* th = a.theta + (int64_t)r * n;
     uint32_t* pw = a.phase ? a.phase + (int64_t)r * n : nullptr;
+    const __amdgpu_buffer_rsrc_t rsrc =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.sell, (short)0, (int)a.sell_bytes, 0x00020000);
+    const int voff = lane * 16;
 
     uint32_t ph[MS][4];
     float sn[MS][4], cs[MS][4], drift[MS][4];
+    int sbase[MS], sdeg[MS];
 
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
         const int slice = wave + k * W;
+        const int2 d = slice < S ? a.desc[slice] : make_int2(0, 0);
+        sbase[k] = __builtin_amdgcn_readfirstlane(d.x);
+        sdeg[k] = __builtin_amdgcn_readfirstlane(d.y);
         const int m = slice * 64 + lane;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -91,7 +107,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             sn[k][j] = sin_turn(u);
             cs[k][j] = cos_turn(u);
             drift[k][j] = 0.0f;
-            if (valid) sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
+            if (slice < S) sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
         }
     }
     __syncthreads();
@@ -107,43 +123,37 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         const float ns = a.sigma[s] * sqrt_dt * kTurnScale;
 
         // ---- phase A: coupling sums over the sliced-ELL rows ----
+        // 4 edges of each of the slice's 4 rows per iteration: 8 16-byte
+        // buffer loads (scalar offsets, no per-lane address math), 16 LDS reads.
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
-            const int slice = wave + k * W;
-            if (slice < S) {
-                const int32_t* d = a.desc + slice * 8;
+            if (wave + k * W < S) {
+                const int D2 = sdeg[k] >> 1;
+                float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int e2 = 0; e2 < D2; e2 += 2) {
+                    int4 v[4][2];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int soff = (sbase[k] + j * D2 + e2) * 1024;
+                        v[j][0] = load_pair(rsrc, voff, soff);
+                        v[j][1] = load_pair(rsrc, voff + 1024, soff);
+                    }
+#pragma unroll
+                    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const float2 p0 = sc_at(smem, v[j][h].x);
+                            const float2 p1 = sc_at(smem, v[j][h].z);
+                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p0.y, A[j]);
+                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p0.x, B[j]);
+                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p1.y, A[j]);
+                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p1.x, B[j]);
+                        }
+                    }
+                }
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const int32_t off = d[j], deg = d[4 + j];
-                    const int2* ep = a.sell + (int64_t)off * 64 + lane;
-                    float A0 = 0.f, B0 = 0.f, A1 = 0.f, B1 = 0.f;
-                    int e = 0;
-                    for (; e + 4 <= deg; e += 4) {
-                        const int2 v0 = ep[(e + 0) * 64];
-                        const int2 v1 = ep[(e + 1) * 64];
-                        const int2 v2 = ep[(e + 2) * 64];
-                        const int2 v3 = ep[(e + 3) * 64];
-                        const float2 p0 = *reinterpret_cast<const float2*>(smem + v0.x);
-                        const float2 p1 = *reinterpret_cast<const float2*>(smem + v1.x);
-                        const float2 p2 = *reinterpret_cast<const float2*>(smem + v2.x);
-                        const float2 p3 = *reinterpret_cast<const float2*>(smem + v3.x);
-                        A0 = __builtin_fmaf(__int_as_float(v0.y), p0.y, A0);
-                        B0 = __builtin_fmaf(__int_as_float(v0.y), p0.x, B0);
-                        A1 = __builtin_fmaf(__int_as_float(v1.y), p1.y, A1);
-                        B1 = __builtin_fmaf(__int_as_float(v1.y), p1.x, B1);
-                        A0 = __builtin_fmaf(__int_as_float(v2.y), p2.y, A0);
-                        B0 = __builtin_fmaf(__int_as_float(v2.y), p2.x, B0);
-                        A1 = __builtin_fmaf(__int_as_float(v3.y), p3.y, A1);
-                        B1 = __builtin_fmaf(__int_as_float(v3.y), p3.x, B1);
-                    }
-                    for (; e < deg; ++e) {
-                        const int2 v = ep[e * 64];
-                        const float2 p = *reinterpret_cast<const float2*>(smem + v.x);
-                        A0 = __builtin_fmaf(__int_as_float(v.y), p.y, A0);
-                        B0 = __builtin_fmaf(__int_as_float(v.y), p.x, B0);
-                    }
-                    const float A = A0 + A1, B = B0 + B1;
-                    const float coup = sn[k][j] * A - cs[k][j] * B;
+                    const float coup = sn[k][j] * A[j] - cs[k][j] * B[j];
                     drift[k][j] = kc * coup + ks * sin_q<QM>(sn[k][j], cs[k][j], ph[k][j], q);
                 }
             }
@@ -155,7 +165,10 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         for (int k = 0; k < MS; ++k) {
             const int slice = wave + k * W;
             const int m = slice * 64 + lane;
-            if (slice < S && 4 * m < n) {
+            // Rows past n are padding: they are advanced and stored like the
+            // others (their slots exist in every plane) but no edge reads them,
+            // which keeps per-lane masks out of the loop.
+            if (slice < S) {
                 float z[4];
                 normals4((uint32_t)m, t, k0, k1, z);
 #pragma unroll
@@ -164,7 +177,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                     ph[k][j] = u;
                     sn[k][j] = sin_turn(u);
                     cs[k][j] = cos_turn(u);
-                    if (4 * m + j < n) sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
+                    sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
                 }
             }
         }
@@ -176,11 +189,10 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             for (int k = 0; k < MS; ++k) {
                 const int slice = wave + k * W;
                 const int m = slice * 64 + lane;
+                if (slice < S) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    if (slice < S && 4 * m + j < n) {
+                    for (int j = 0; j < 4; ++j)
                         col8[j * plane + m] = (unsigned char)nearest_state(ph[k][j], q);
-                    }
                 }
             }
             __syncthreads();
@@ -190,20 +202,20 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 const int slice = wave + k * W;
                 if (slice < S) {
                     const int m = slice * 64 + lane;
-                    const int32_t* d = a.desc + slice * 8;
+                    const int D2 = sdeg[k] >> 1;
+                    // padding rows hold only J = 0 entries and add nothing
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        if (4 * m + j >= n) continue;
                         const int ci = col8[j * plane + m];
-                        const int32_t off = d[j], deg = d[4 + j];
-                        const int2* ep = a.sell + (int64_t)off * 64 + lane;
                         double row = 0.0;
-                        for (int e = 0; e < deg; ++e) {
-                            const int2 v = ep[e * 64];
-                            const int cj = col8[v.x >> 3];
-                            const float w = __int_as_float(v.y);
-                            const float term = (q == 2) ? (ci == cj ? w : -w) : (ci == cj ? w : 0.f);
-                            row += (double)term;
+                        for (int e2 = 0; e2 < D2; ++e2) {
+                            const int4 v = load_pair(rsrc, voff, (sbase[k] + j * D2 + e2) * 1024);
+                            const int c0 = col8[v.x >> 3], c1 = col8[v.z >> 3];
+                            const float w0 = __int_as_float(v.y), w1 = __int_as_float(v.w);
+                            const float t0 = (q == 2) ? (ci == c0 ? w0 : -w0) : (ci == c0 ? w0 : 0.f);
+                            const float t1 = (q == 2) ? (ci == c1 ? w1 : -w1) : (ci == c1 ? w1 : 0.f);
+                            row += (double)t0;
+                            row += (double)t1;
                         }
                         acc += row;
                     }
@@ -296,6 +308,8 @@ size_t lds_bytes(int plane, int tb) {
     return b;
 }
 
+constexpr uint64_t kMaxSellBytes = 0x7fffffffull;
+
 // Pick the variant: fewest waves that still cover every slice with the
 // registers of one variant, preferring 8 waves per workgroup.
 const Variant* pick_variant(int S, int tb_hint) {
@@ -323,6 +337,7 @@ int env_int(const char* name, int dflt) {
 bool persistent_sparse_fits(const Problem* p) {
     if (p->dense || p->sell_slices == 0) return false;
     if (lds_bytes(p->sell_slices * 64, 1024) > kLdsLimit) return false;
+    if ((uint64_t)p->sell_entries * 8 > kMaxSellBytes) return false;
     return pick_variant(p->sell_slices, 0) != nullptr;
 }
 
@@ -336,8 +351,9 @@ int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const flo
     if (!v || !persistent_sparse_fits(p))
         return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
     PersistArgs a{};
-    a.sell = p->d_sell;
+    a.sell = reinterpret_cast<const int4*>(p->d_sell);
     a.desc = p->d_sell_desc;
+    a.sell_bytes = (uint32_t)(p->sell_entries * 8);
     a.S = S;
     a.plane = S * 64;
     a.n = p->n;

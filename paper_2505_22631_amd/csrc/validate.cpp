@@ -124,28 +124,23 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
     const int32_t quads = (n + 3) / 4;
     const int32_t S = (quads + kSliceQuads - 1) / kSliceQuads;
     out.slices = S;
-    out.desc.assign((size_t)S * 8, 0);
-    int64_t off = 0;
+    out.desc.assign((size_t)S, int2{0, 0});
+    int64_t rows4 = 0;  // running offset in int4 rows (64 int4 per row)
     for (int32_t s = 0; s < S; ++s) {
-        for (int j = 0; j < 4; ++j) {
-            int32_t mx = 0;
-            for (int l = 0; l < kSliceQuads; ++l) {
-                const int64_t i = 4LL * (s * kSliceQuads + l) + j;
-                if (i < n) mx = std::max<int32_t>(mx, (int32_t)(row_ptr[i + 1] - row_ptr[i]));
-            }
-            out.desc[s * 8 + j] = (int32_t)off;
-            out.desc[s * 8 + 4 + j] = mx;
-            off += mx;
-        }
+        int32_t mx = 0;
+        for (int64_t i = 4LL * s * kSliceQuads; i < std::min<int64_t>(n, 4LL * (s + 1) * kSliceQuads); ++i)
+            mx = std::max<int32_t>(mx, (int32_t)(row_ptr[i + 1] - row_ptr[i]));
+        const int32_t deg = (mx + 3) & ~3;
+        out.desc[s] = int2{(int32_t)rows4, deg};
+        rows4 += 4LL * deg / 2;
     }
-    // LDS position of oscillator i: plane (i % 4) of length S*64, slot i / 4,
-    // so the 64 lanes of a wave touch 64 consecutive (sin, cos) pairs.
+    // LDS position of oscillator i: plane (i % 4) of length S*64, slot i / 4.
     const int64_t plane = (int64_t)S * kSliceQuads;
     auto lds_off = [plane](int64_t i) { return (int32_t)(8 * ((i & 3) * plane + (i >> 2))); };
-    out.entries.assign((size_t)off * kSliceQuads, int2{0, 0});
+    out.entries.assign((size_t)rows4 * kSliceQuads * 2, int2{0, 0});
     for (int32_t s = 0; s < S; ++s) {
+        const int32_t base = out.desc[s].x, deg = out.desc[s].y;
         for (int j = 0; j < 4; ++j) {
-            const int32_t base = out.desc[s * 8 + j], deg = out.desc[s * 8 + 4 + j];
             for (int l = 0; l < kSliceQuads; ++l) {
                 const int64_t i = 4LL * (s * kSliceQuads + l) + j;
                 const int32_t self = (int32_t)std::min<int64_t>(i, n - 1);
@@ -161,7 +156,8 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
                         v.x = lds_off(self);
                         v.y = 0;
                     }
-                    out.entries[(size_t)(base + e) * kSliceQuads + l] = v;
+                    const int64_t q4 = ((int64_t)base + j * (deg / 2) + e / 2) * kSliceQuads + l;
+                    out.entries[(size_t)(q4 * 2 + (e & 1))] = v;
                 }
             }
         }
