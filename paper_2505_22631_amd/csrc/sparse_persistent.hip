@@ -88,7 +88,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     const int voff = lane * 16;
 
     uint32_t ph[MS][4];
-    float sn[MS][4], cs[MS][4], drift[MS][4];
+    float drift[MS][4];
     int sbase[MS], sdeg[MS];
 
 #pragma unroll
@@ -104,10 +104,8 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             const bool valid = slice < S && i < n;
             const uint32_t u = valid ? (pw ? pw[i] : phase_from_theta(th[i])) : 0u;
             ph[k][j] = u;
-            sn[k][j] = sin_turn(u);
-            cs[k][j] = cos_turn(u);
             drift[k][j] = 0.0f;
-            if (slice < S) sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
+            if (slice < S) sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
         }
     }
     __syncthreads();
@@ -151,10 +149,12 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                         }
                     }
                 }
+                const int m = (wave + k * W) * 64 + lane;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const float coup = sn[k][j] * A[j] - cs[k][j] * B[j];
-                    drift[k][j] = kc * coup + ks * sin_q<QM>(sn[k][j], cs[k][j], ph[k][j], q);
+                    const float2 own = sc[j * plane + m];
+                    const float coup = own.x * A[j] - own.y * B[j];
+                    drift[k][j] = kc * coup + ks * sin_q<QM>(own.x, own.y, ph[k][j], q);
                 }
             }
         }
@@ -169,15 +169,18 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             // others (their slots exist in every plane) but no edge reads them,
             // which keeps per-lane masks out of the loop.
             if (slice < S) {
+                // The quad index and the key are re-materialised every step
+                // (empty asm) so partial Philox rounds are not precomputed
+                // and kept live in registers across the whole run.
+                uint32_t mm = (uint32_t)m, kk0 = k0, kk1 = k1;
+                asm volatile("" : "+v"(mm), "+s"(kk0), "+s"(kk1));
                 float z[4];
-                normals4((uint32_t)m, t, k0, k1, z);
+                normals4(mm, t, kk0, kk1, z);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t u = advance(ph[k][j], __builtin_fmaf(ns, z[j], drift[k][j]));
                     ph[k][j] = u;
-                    sn[k][j] = sin_turn(u);
-                    cs[k][j] = cos_turn(u);
-                    sc[j * plane + m] = make_float2(sn[k][j], cs[k][j]);
+                    sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
                 }
             }
         }
@@ -295,6 +298,7 @@ const Variant kVariants[] = {
     OIM_VARIANT(256, 6),  OIM_VARIANT(256, 8),  OIM_VARIANT(256, 10), OIM_VARIANT(256, 12),
     OIM_VARIANT(512, 1),  OIM_VARIANT(512, 2),  OIM_VARIANT(512, 3),  OIM_VARIANT(512, 4),
     OIM_VARIANT(512, 5),  OIM_VARIANT(512, 6),  OIM_VARIANT(512, 8),  OIM_VARIANT(512, 10),
+    OIM_VARIANT(640, 4),  OIM_VARIANT(768, 3),  OIM_VARIANT(768, 4),
     OIM_VARIANT(1024, 1), OIM_VARIANT(1024, 2), OIM_VARIANT(1024, 3), OIM_VARIANT(1024, 4),
     OIM_VARIANT(1024, 5),
 };

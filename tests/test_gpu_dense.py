@@ -1,0 +1,107 @@
+"""GPU parity of the dense (all-to-all) path: coupling as a BF16 three-term
+split GEMM on the matrix cores, against the FP64 oracle's all-pairs loop."""
+import numpy as np
+import pytest
+
+import synth
+from _util import DT, ramp_schedule, wrapdiff
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_22631_amd as m
+    m.lib()
+    return m
+
+
+def _run(oim, prob, th0, K, Ks, sg, sd, q, step0=0, readout_every=0, want_best=False):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(th0)).cuda()
+    out = oim.run(prob, t, torch.from_numpy(K).cuda(), torch.from_numpy(Ks).cuda(),
+                  torch.from_numpy(sg).cuda(),
+                  torch.from_numpy(np.ascontiguousarray(sd, np.uint64)).cuda(), q=q, dt=DT,
+                  readout_every=readout_every, flags=oim.OIM_PREC_BF16X3, step0=step0,
+                  want_best=want_best)
+    torch.cuda.synchronize()
+    return t.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def _bf16x3_bound(J, K, steps_used):
+    """Coupling error bound of the split product per step, |dc_i| <=
+    sum_j |J_ij| * 2^-15 (two dropped/rounded terms of 2^-16 relative each),
+    summed over the steps (no chaotic amplification allowance)."""
+    rowsum = np.abs(J).sum(axis=1).max()
+    return float(DT * np.sum(K[:steps_used]) * rowsum * 2.0 ** -15)
+
+
+@pytest.mark.parametrize("n,R,q", [(200, 5, 2), (256, 64, 2), (130, 3, 3)])
+def test_dense_parity_sk(oim, orc, n, R, q):
+    J = synth.sk_dense(n, seed=3)
+    with oim.Problem.from_dense(J) as prob:
+        rowsum = prob.info["max_abs_row_sum"]
+        K, Ks, sg = ramp_schedule(rowsum, q, 1000, 100)
+        th0 = synth.theta0(R, n, seed=21)
+        sd = synth.seeds(R, 7)
+        got, _ = _run(oim, prob, th0, K, Ks, sg, sd, q, step0=50)
+    want = orc.run_dense(J.astype(np.float64), th0, q=q, dt=DT, K=K, Ks=Ks, sigma=sg, seeds=sd,
+                         step0=50)
+    err = wrapdiff(got, want).max()
+    bound = _bf16x3_bound(J.astype(np.float64), K, 100)
+    print(f"dense n={n} R={R} q={q}: max |dtheta| = {err:.3e} rad (split bound {bound:.2e})",
+          flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < max(1e-5, 20 * bound)
+
+
+def test_dense_matches_sparse_on_same_coupling(oim, orc):
+    # the same J through the dense BF16x3 path and the FP32 sparse path
+    g = synth.erdos_renyi(300, 0.1, seed=4)
+    Jd = np.zeros((300, 300), np.float32)
+    ei, ej, w = g.upper_edges()
+    Jd[ei, ej] = -w
+    Jd[ej, ei] = -w
+    K, Ks, sg = ramp_schedule(synth.gershgorin(g), 2, 1000, 100)
+    th0 = synth.theta0(4, 300, seed=5)
+    sd = synth.seeds(4, 1)
+    with oim.Problem.from_dense(Jd) as pd, oim.Problem.from_csr(300, g.row_ptr, g.col, -g.w) as ps:
+        a, _ = _run(oim, pd, th0, K, Ks, sg, sd, 2)
+        import torch
+        t = torch.from_numpy(th0.copy()).cuda()
+        oim.run(ps, t, torch.from_numpy(K).cuda(), torch.from_numpy(Ks).cuda(),
+                torch.from_numpy(sg).cuda(), torch.from_numpy(sd).cuda(), q=2, dt=DT)
+        b = t.cpu().numpy()
+    # unit weights are exact in BF16, so the split only rounds sin/cos
+    assert wrapdiff(a, b).max() < 1e-5
+
+
+def test_dense_in_run_readout(oim, orc):
+    n, R = 160, 4
+    J = synth.sk_dense(n, seed=8)
+    with oim.Problem.from_dense(J) as prob:
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 2, 120)
+        th0 = synth.theta0(R, n, seed=2)
+        th, ro = _run(oim, prob, th0, K, Ks, sg, synth.seeds(R, 3), 2, readout_every=40,
+                      want_best=True)
+    rp, cl, Jv = orc.dense_to_csr(J)
+    tr = ro["trace"]
+    assert tr.shape == (3, R)
+    np.testing.assert_array_equal(ro["best_h"], tr.min(axis=0))
+    for r in range(R):
+        h = orc.h_model(rp, cl, Jv, 2, ro["best_colour"][r])
+        assert abs(h - ro["best_h"][r]) < 1e-9 * max(1.0, np.abs(J).sum())
+
+
+def test_dense_rejects_fp32_precision(oim):
+    import torch
+    J = synth.sk_dense(64, seed=1)
+    with oim.Problem.from_dense(J) as prob:
+        t = torch.zeros((1, 64), device="cuda")
+        z = torch.zeros(3, device="cuda")
+        with pytest.raises(oim.OimError):
+            oim.run(prob, t, z, z, z, torch.zeros(1, dtype=torch.uint64, device="cuda"), q=2,
+                    dt=DT)
