@@ -1,12 +1,409 @@
-// stepwise.hip -- one kernel per Euler-Maruyama step, state in device memory.
+// stepwise.hip -- Algorithm 1 with the replica state in device memory, one
+// kernel per Euler-Maruyama step, for replicas too large for the
+// LDS-resident kernel.
+//
+// Layout: replica index fastest, [n][Rp] (Rp = R rounded up to 64), for the
+// phase words and for two (sin, cos) tables (ping-pong: step t reads table
+// t%2 and writes table (t+1)%2, which keeps the synchronous update of
+// Algorithm 1).  A wave owns one quad (4 consecutive oscillators) and 64
+// replicas: CSR entries are wave-uniform (scalar loads) and each neighbour
+// gather is one coalesced 512-byte load.  Lane r draws the quad's four
+// normals with one Philox call keyed by replica r's seed.
+//
+// The step loop is captured once into a hipGraph of `chunk` step kernels
+// plus a node that advances a device-resident step base; the executable
+// graph is replayed ceil(steps / chunk) times (step kernels past the last
+// step return at once).  In-run readouts are graph nodes too (chunk is a
+// multiple of the readout period), with the final partial readout launched
+// after the replays.
+#include <float.h>
+
+#include <algorithm>
+#include <cmath>
+
 #include "internal.hpp"
+#include "noise.hpp"
+#include "phase.hpp"
 
 namespace oim {
 
-int launch_stepwise_sparse(Problem*, const oim_run_cfg*, const float*, const float*, const float*,
-                           const uint64_t*, int64_t, float*, uint32_t*, const oim_readout*,
-                           hipStream_t) {
-    return set_error(OIM_E_UNSUPPORTED, "replica too large for the LDS-resident kernel");
+namespace {
+
+constexpr int kQuadsPerBlock = 4;  // one per wave, 256 threads
+
+struct StepArgs {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const float* J;
+    uint32_t* U;          // [np][Rp]
+    const float2* tin;    // [np][Rp]
+    float2* tout;
+    const float* K;
+    const float* Ks;
+    const float* sigma;
+    const uint64_t* seeds;
+    const int* base;      // device step base (local index of node 0 of the chunk)
+    int k;                // position of this node in the chunk
+    int steps, n, R, Rp, q;
+    int64_t step0;
+    float dt;
+};
+
+template <int QM>
+__global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
+    const int s = *a.base + a.k;
+    if (s >= a.steps) return;
+    const int lane = threadIdx.x & 63;
+    const int m = blockIdx.x * kQuadsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (4 * m >= a.n) return;
+    const int r = blockIdx.y * 64 + lane;
+    const int Rp = a.Rp, q = QM ? QM : a.q;
+    const uint32_t t = (uint32_t)(a.step0 + s);
+    const float sqrt_dt = __builtin_sqrtf(a.dt);
+    const float kc = -a.dt * a.K[s] * kTurnScale;
+    const float ks = -a.dt * a.Ks[s] * kTurnScale;
+    const float ns = a.sigma[s] * sqrt_dt * kTurnScale;
+    const uint64_t seed = r < a.R ? a.seeds[r] : 0ull;
+    float z[4];
+    normals4((uint32_t)m, t, (uint32_t)seed, (uint32_t)(seed >> 32), z);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = 4 * m + j;
+        if (i >= a.n) break;
+        const int64_t e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
+        float A0 = 0.f, B0 = 0.f, A1 = 0.f, B1 = 0.f;
+        int64_t e = e0;
+        for (; e + 2 <= e1; e += 2) {
+            const int c0 = a.col[e], c1 = a.col[e + 1];
+            const float w0 = a.J[e], w1 = a.J[e + 1];
+            const float2 p0 = a.tin[(size_t)c0 * Rp + r];
+            const float2 p1 = a.tin[(size_t)c1 * Rp + r];
+            A0 = __builtin_fmaf(w0, p0.y, A0);
+            B0 = __builtin_fmaf(w0, p0.x, B0);
+            A1 = __builtin_fmaf(w1, p1.y, A1);
+            B1 = __builtin_fmaf(w1, p1.x, B1);
+        }
+        if (e < e1) {
+            const int c0 = a.col[e];
+            const float w0 = a.J[e];
+            const float2 p0 = a.tin[(size_t)c0 * Rp + r];
+            A0 = __builtin_fmaf(w0, p0.y, A0);
+            B0 = __builtin_fmaf(w0, p0.x, B0);
+        }
+        const size_t idx = (size_t)i * Rp + r;
+        const float2 own = a.tin[idx];
+        const float A = A0 + A1, B = B0 + B1;
+        const float coup = own.x * A - own.y * B;
+        const uint32_t u0 = a.U[idx];
+        const float drift = kc * coup + ks * sin_q<QM>(own.x, own.y, u0, q);
+        const uint32_t u = advance(u0, __builtin_fmaf(ns, z[j], drift));
+        a.U[idx] = u;
+        a.tout[idx] = make_float2(sin_turn(u), cos_turn(u));
+    }
+}
+
+__global__ void advance_base_kernel(int* base, int chunk) { *base += chunk; }
+
+// [R][n] theta or phase words -> [np][Rp] phase words and table (both
+// tables get the initial values so padding is finite everywhere).
+__global__ __launch_bounds__(256) void stepwise_init_kernel(const float* theta, const uint32_t* phase,
+                                                            uint32_t* U, float2* t0, float2* t1,
+                                                            int n, int R, int np, int Rp) {
+    const size_t total = (size_t)np * Rp;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / Rp), r = (int)(e % Rp);
+        uint32_t u = 0;
+        if (i < n && r < R) {
+            const size_t src = (size_t)r * n + i;
+            u = phase ? phase[src] : phase_from_theta(theta[src]);
+        }
+        U[e] = u;
+        const float2 v = make_float2(sin_turn(u), cos_turn(u));
+        t0[e] = v;
+        t1[e] = v;
+    }
+}
+
+__global__ __launch_bounds__(256) void stepwise_final_kernel(const uint32_t* U, float* theta,
+                                                             uint32_t* phase, int n, int R, int Rp) {
+    const size_t total = (size_t)R * n;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / n), i = (int)(e % n);
+        const uint32_t u = U[(size_t)i * Rp + r];
+        theta[e] = theta_from_phase(u);
+        if (phase) phase[e] = u;
+    }
+}
+
+struct ReadArgs {
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const float* J;
+    const uint32_t* U;
+    double* part;  // [gridDim.x][Rp]
+    const int* base;
+    int k, steps, n, Rp, q;
+};
+
+// Partial sums of sum_i sum_{j in N(i)} J_ij term(k_i, k_j) per block of quads
+// and replica (term = s_i s_j for q = 2, delta(k_i, k_j) for q >= 3).
+__global__ __launch_bounds__(256) void stepwise_readout_kernel(ReadArgs a) {
+    __shared__ double red[kQuadsPerBlock][64];
+    const int s = *a.base + a.k;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = blockIdx.y * 64 + lane;
+    double acc = 0.0;
+    if (s < a.steps) {
+        const int m = blockIdx.x * kQuadsPerBlock + wave;
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * m + j;
+            if (i >= a.n) break;
+            const int ci = nearest_state(a.U[(size_t)i * a.Rp + r], a.q);
+            for (int64_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
+                const int cj = nearest_state(a.U[(size_t)a.col[e] * a.Rp + r], a.q);
+                const double w = (double)a.J[e];
+                acc += (a.q == 2) ? (ci == cj ? w : -w) : (ci == cj ? w : 0.0);
+            }
+        }
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && s < a.steps) {
+        double tot = 0.0;
+        for (int w = 0; w < kQuadsPerBlock; ++w) tot += red[w][lane];
+        a.part[(size_t)blockIdx.x * a.Rp + r] = tot;
+    }
+}
+
+struct BestArgs {
+    const double* part;
+    int nblocks;
+    const uint32_t* U;
+    double* trace;
+    double* best;     // running best (workspace)
+    int32_t* best_at; // running best step (workspace)
+    int8_t* best_colour;
+    const int* base;
+    int k, steps, M, n, R, Rp, q;
+    int64_t step0;
+    int last;         // 1 when this node reads out after the last step (forced)
+};
+
+// One workgroup per replica: H = -1/2 sum of the partials (fixed order),
+// trace entry, best-so-far and the colours of a new best.
+__global__ __launch_bounds__(256) void stepwise_best_kernel(BestArgs a) {
+    __shared__ int improved;
+    const int s = a.last ? a.steps - 1 : *a.base + a.k;
+    if (s >= a.steps) return;
+    const int r = blockIdx.x;
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int b = 0; b < a.nblocks; ++b) tot += a.part[(size_t)b * a.Rp + r];
+        const double H = -0.5 * tot;
+        const int kread = (s + a.M) / a.M - 1;
+        if (a.trace) a.trace[(size_t)kread * a.R + r] = H;
+        improved = (kread == 0 || H < a.best[r]) ? 1 : 0;
+        if (improved) {
+            a.best[r] = H;
+            a.best_at[r] = (int32_t)(a.step0 + s + 1);
+        }
+    }
+    __syncthreads();
+    if (improved && a.best_colour)
+        for (int i = threadIdx.x; i < a.n; i += blockDim.x)
+            a.best_colour[(size_t)r * a.n + i] = (int8_t)nearest_state(a.U[(size_t)i * a.Rp + r], a.q);
+}
+
+int check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? OIM_OK : hip_error(e, what);
+}
+
+// releases what a failed capture left behind
+struct GraphGuard {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t x = nullptr;
+    ~GraphGuard() {
+        if (x) hipGraphExecDestroy(x);
+        if (g) hipGraphDestroy(g);
+    }
+};
+
+}  // namespace
+
+int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                           const float* sigma, const uint64_t* seeds, int64_t step0,
+                           float* theta, uint32_t* phase, const oim_readout* ro,
+                           hipStream_t stream) {
+    const int n = p->n, R = cfg->R, steps = cfg->steps, M = cfg->readout_every;
+    const int Rp = (R + 63) / 64 * 64;
+    const int quads = (n + 3) / 4;
+    const int np = quads * 4;
+    const int gx = (quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
+    const size_t cells = (size_t)np * Rp;
+    // chunk: a multiple of the readout period, about 64 steps
+    int chunk = std::min(steps, 64);
+    if (M > 0) chunk = std::max(1, (std::min(steps, std::max(64, M)) / M)) * M;
+    chunk = std::max(1, std::min(chunk, steps));
+    const size_t need = cells * (4 + 8 + 8) + (size_t)gx * Rp * 8 + (size_t)R * 12 + 256;
+    if (p->work_bytes < need) {
+        hipFree(p->d_work);
+        p->d_work = nullptr;
+        p->work_bytes = 0;
+        hipError_t e = hipMalloc(&p->d_work, need);
+        if (e != hipSuccess) {
+            p->d_work = nullptr;
+            return e == hipErrorOutOfMemory ? set_error(OIM_E_NOMEM, "stepwise workspace")
+                                            : hip_error(e, "hipMalloc stepwise workspace");
+        }
+        p->work_bytes = need;
+    }
+    unsigned char* w = static_cast<unsigned char*>(p->d_work);
+    uint32_t* U = reinterpret_cast<uint32_t*>(w);
+    float2* T0 = reinterpret_cast<float2*>(w + cells * 4);
+    float2* T1 = T0 + cells;
+    double* part = reinterpret_cast<double*>(T1 + cells);
+    double* best = part + (size_t)gx * Rp;
+    int32_t* best_at = reinterpret_cast<int32_t*>(best + R);
+    int* base = reinterpret_cast<int*>(best_at + R + 16);
+
+    hipLaunchKernelGGL(stepwise_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U, T0,
+                       T1, n, R, np, Rp);
+    int st = check_launch("stepwise_init_kernel");
+    if (st) return st;
+    hipError_t e = hipMemsetAsync(base, 0, sizeof(int), stream);
+    if (e != hipSuccess) return hip_error(e, "reset step base");
+
+    using StepFn = void (*)(StepArgs);
+    StepFn fn = cfg->q == 2 ? stepwise_step_kernel<2>
+                            : cfg->q == 3 ? stepwise_step_kernel<3> : stepwise_step_kernel<0>;
+    StepArgs sa{};
+    sa.row_ptr = p->d_row_ptr;
+    sa.col = p->d_col;
+    sa.J = p->d_J;
+    sa.U = U;
+    sa.K = K;
+    sa.Ks = Ks;
+    sa.sigma = sigma;
+    sa.seeds = seeds;
+    sa.base = base;
+    sa.steps = steps;
+    sa.n = n;
+    sa.R = R;
+    sa.Rp = Rp;
+    sa.q = cfg->q;
+    sa.step0 = step0;
+    sa.dt = cfg->dt;
+    ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, base, 0, steps, n, Rp, cfg->q};
+    BestArgs ba{};
+    ba.part = part;
+    ba.nblocks = gx;
+    ba.U = U;
+    ba.trace = ro ? ro->trace : nullptr;
+    ba.best = best;
+    ba.best_at = best_at;
+    ba.best_colour = ro ? ro->best_colour : nullptr;
+    ba.base = base;
+    ba.steps = steps;
+    ba.M = M;
+    ba.n = n;
+    ba.R = R;
+    ba.Rp = Rp;
+    ba.q = cfg->q;
+    ba.step0 = step0;
+
+    // Record one chunk: step kernels (with readouts where due) and the base
+    // advance.  Table parity alternates per step; chunk is even or the parity
+    // is carried by swapping the tables between replays.
+    auto record_chunk = [&](hipStream_t s, bool parity) -> int {
+        for (int k = 0; k < chunk; ++k) {
+            const bool odd = ((k & 1) != 0) != parity;
+            sa.tin = odd ? T1 : T0;
+            sa.tout = odd ? T0 : T1;
+            sa.k = k;
+            hipLaunchKernelGGL(fn, dim3(gx, Rp / 64), dim3(256), 0, s, sa);
+            int rc = check_launch("stepwise_step_kernel");
+            if (rc) return rc;
+            if (M > 0 && (k + 1) % M == 0) {
+                ra.k = k;
+                hipLaunchKernelGGL(stepwise_readout_kernel, dim3(gx, Rp / 64), dim3(256), 0, s, ra);
+                if ((rc = check_launch("stepwise_readout_kernel"))) return rc;
+                ba.k = k;
+                ba.last = 0;
+                hipLaunchKernelGGL(stepwise_best_kernel, dim3(R), dim3(256), 0, s, ba);
+                if ((rc = check_launch("stepwise_best_kernel"))) return rc;
+            }
+        }
+        hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, s, base, chunk);
+        return check_launch("advance_base_kernel");
+    };
+
+    const int replays = (steps + chunk - 1) / chunk;
+    const bool flip = (chunk & 1) != 0;  // an odd chunk flips the table parity each replay
+    GraphGuard g[2];
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_error(e, "capture stream");
+    for (int par = 0; par < (flip ? 2 : 1); ++par) {
+        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            hipStreamDestroy(cap);
+            return hip_error(e, "hipStreamBeginCapture");
+        }
+        st = record_chunk(cap, par == 1);
+        e = hipStreamEndCapture(cap, &g[par].g);
+        if (st || e != hipSuccess) {
+            hipStreamDestroy(cap);
+            return st ? st : hip_error(e, "hipStreamEndCapture");
+        }
+        e = hipGraphInstantiate(&g[par].x, g[par].g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipStreamDestroy(cap);
+            return hip_error(e, "hipGraphInstantiate");
+        }
+    }
+    hipStreamDestroy(cap);
+    for (int c = 0; c < replays; ++c) {
+        e = hipGraphLaunch(g[flip ? (c & 1) : 0].x, stream);
+        if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+    }
+    // readout after the last step when steps is not a multiple of M
+    if (M > 0 && steps % M != 0) {
+        ra.k = 0;
+        // the base now points past the end; a node reading "last" ignores it
+        BestArgs bl = ba;
+        bl.last = 1;
+        ReadArgs rl = ra;
+        rl.base = nullptr;
+        // readout kernel with an explicit step: reuse the base slot
+        e = hipMemsetAsync(base, 0, sizeof(int), stream);
+        if (e != hipSuccess) return hip_error(e, "reset step base");
+        rl.base = base;
+        rl.k = steps - 1;
+        hipLaunchKernelGGL(stepwise_readout_kernel, dim3(gx, Rp / 64), dim3(256), 0, stream, rl);
+        if ((st = check_launch("stepwise_readout_kernel"))) return st;
+        hipLaunchKernelGGL(stepwise_best_kernel, dim3(R), dim3(256), 0, stream, bl);
+        if ((st = check_launch("stepwise_best_kernel"))) return st;
+    }
+    if (ro && M > 0 && steps > 0) {
+        if (ro->best_h) {
+            e = hipMemcpyAsync(ro->best_h, best, sizeof(double) * R, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_error(e, "best_h copy");
+        }
+        if (ro->best_step) {
+            e = hipMemcpyAsync(ro->best_step, best_at, sizeof(int32_t) * R, hipMemcpyDeviceToDevice, stream);
+            if (e != hipSuccess) return hip_error(e, "best_step copy");
+        }
+    }
+    hipLaunchKernelGGL(stepwise_final_kernel, dim3(2048), dim3(256), 0, stream, U, theta, phase, n, R, Rp);
+    st = check_launch("stepwise_final_kernel");
+    if (st) return st;
+    // the graphs are destroyed on return; wait until the replays are done
+    e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_error(e, "stepwise sync");
+    return OIM_OK;
 }
 
 }  // namespace oim

@@ -265,3 +265,55 @@ def test_in_run_readout_trace(dev, oim, orc):
         assert tr[-1, r] == orc.h_model(g.row_ptr, g.col, J, 2, _colours_from_words(w[r], 2))
     # same trajectory with and without the readout
     np.testing.assert_array_equal(th, th2)
+
+
+# ---------------------------------------------------------------- stepwise ----
+def test_stepwise_parity(dev, oim, orc):
+    # the device-memory, graph-captured loop on the same cases
+    for g, J, q, R, total in [
+        (c1_graph(), None, 2, 3, 1000),
+        (c2_graph(), None, 2, 70, 10000),
+        (synth.planted_colouring(503, 4.6, 3, seed=2)[0], "colour", 3, 2, 5000),
+        (synth.random_small(97, 0.08, seed=5, weights="real"), None, 5, 2, 1000),
+    ]:
+        Jv = -np.ones(g.nnz, np.float32) if J == "colour" else -g.w
+        prob = _problem(oim, g, Jv)
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, total, 101)
+        th0 = synth.theta0(R, g.n, seed=31)
+        sd = synth.seeds(R, 4)
+        got, _ = _gpu_run(oim, prob, th0, K, Ks, sg, sd, q, step0=9, flags=oim.OIM_LOOP_STEPWISE)
+        want = orc.run_csr(g.row_ptr, g.col, Jv, th0, q=q, dt=DT, K=K, Ks=Ks, sigma=sg,
+                           seeds=sd, step0=9)
+        err = wrapdiff(got, want).max()
+        print(f"stepwise n={g.n} q={q} R={R}: max |dtheta| = {err:.3e} rad", flush=True)
+        assert err < TOL_RAD
+        prob.close()
+
+
+def test_stepwise_readout_and_resume(dev, oim, orc):
+    g = c1_graph()
+    J = -g.w
+    prob = _problem(oim, g, J)
+    K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 2, 230)
+    th0 = synth.theta0(3, g.n, seed=6)
+    w0 = _phase_words(th0)
+    F = oim.OIM_LOOP_STEPWISE
+    th, ro, w = _gpu_run(oim, prob, th0, K, Ks, sg, synth.seeds(3, 2), 2, readout_every=50,
+                         want_best=True, flags=F, phase=w0)
+    tr = ro["trace"]
+    assert tr.shape == (5, 3)
+    np.testing.assert_array_equal(ro["best_h"], tr.min(axis=0))
+    for r in range(3):
+        k = int(np.argmin(tr[:, r]))
+        assert ro["best_step"][r] == min(50 * (k + 1), 230)
+        assert orc.h_model(g.row_ptr, g.col, J, 2, ro["best_colour"][r]) == ro["best_h"][r]
+        assert tr[-1, r] == orc.h_model(g.row_ptr, g.col, J, 2, _colours_from_words(w[r], 2))
+    # split run with phase words == uninterrupted run, bit for bit
+    _, _, wa = _gpu_run(oim, prob, th0, K[:77], Ks[:77], sg[:77], synth.seeds(3, 2), 2, flags=F,
+                        phase=w0)
+    _, _, wb = _gpu_run(oim, prob, th0, K[77:], Ks[77:], sg[77:], synth.seeds(3, 2), 2,
+                        step0=77, flags=F, phase=wa)
+    np.testing.assert_array_equal(w, wb)
+    # and the persistent kernel reaches the same phases within the parity bound
+    th_p, _ = _gpu_run(oim, prob, th0, K, Ks, sg, synth.seeds(3, 2), 2)
+    assert wrapdiff(th_p, th).max() < TOL_RAD
