@@ -132,6 +132,77 @@ def cpu_baseline(wl, target_s=15.0):
                       f"({el:.1f} s, FP64, OpenMP over replicas, {_cpu_model()})"}
 
 
+MFMA_BF16_PEAK_TFLOPS = 2500.0
+
+
+def bench_dense(args):
+    """Dense SK Ising: n = 4096, J_ij ~ N(0, 1/n) (seed 3), 512 replicas,
+    coupling as a BF16x3 GEMM on the matrix cores, 1000 steps."""
+    import torch
+    import paper_2505_22631_amd as oim
+    import synth
+    n, R, steps, q = 4096, 512, args.dense_steps, 2
+    dt = float(np.float32(0.01))
+    J = synth.sk_dense(n, seed=3)
+    dev = torch.device("cuda:0")
+    prob = oim.Problem.from_dense(J)
+    kmax = 2.0 * 0.5 / (dt * prob.info["max_abs_row_sum"])
+    ksmax = 0.5 / (dt * q)
+    K = torch.from_numpy(synth.ramp(0.0, kmax, steps)).to(dev)
+    Ks = torch.from_numpy(synth.triangle(ksmax, 5, steps)).to(dev)
+    sg = torch.from_numpy(synth.const(0.1, steps)).to(dev)
+    th_init = torch.from_numpy(synth.theta0(R, n, seed=100)).to(dev)
+    seeds = torch.from_numpy(synth.seeds(R, 0)).to(dev)
+    theta = torch.empty_like(th_init)
+    stream = torch.cuda.current_stream()
+
+    def solve(ev=None):
+        theta.copy_(th_init)
+        if ev:
+            ev[0].record(stream)
+        oim.oim_run(prob.handle, n, theta, K, Ks, sg, seeds, q=q, dt=dt,
+                    flags=oim.OIM_PREC_BF16X3)
+        if ev:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        solve(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_per_step = wall / args.steps * 1e3
+    eu = float(n) * (n - 1) * R * steps
+    col = oim.oim_round(q, theta)
+    hm, _ = oim.oim_energy(prob.handle, q, colour=col)
+    e_per_spin = float(hm.min().item()) / n
+    # executed MFMA flops of the BF16x3 coupling: 3 products of an n x n by
+    # n x 2R GEMM per step
+    flops_step = 3.0 * 2.0 * n * n * 2 * R
+    achieved = flops_step * steps / (run_ms * 1e-3) / 1e12
+    out = {
+        "metric": "edge-updates/s & time-to-99%-best-cut, batched vs plain, 1 MI355X",
+        "value": eu / (ms_per_step * 1e-3), "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
+        "data": "synthetic",
+        "config": {"workload": "dense SK Ising n=4096, 512 replicas, BF16x3 MFMA coupling",
+                   "n": n, "replicas": R, "em_steps": steps, "K_max": kmax, "Ks_max": ksmax},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
+                     "traffic": None, "kernel": "dense_step_kernel (per run, incl. epilogue)",
+                     "run_ms": run_ms, "flops_per_step": flops_step},
+        "best_energy_per_spin": e_per_spin,
+    }
+    print(json.dumps(out))
+    prob.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +212,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", type=int, default=8,
                     help="replicas to time in the plain one-launch-per-replica loop")
+    ap.add_argument("--dense-steps", type=int, default=1000)
     ap.add_argument("--ref-mult", type=int, default=10,
                     help="length multiple of the untimed reference run that sets best_ref")
     args = ap.parse_args()
@@ -149,6 +221,9 @@ def main():
               "(replicas shard across GPUs with no exchange, see the design notes)",
               file=sys.stderr)
         raise SystemExit(2)
+
+    if args.workload == "sk4096":
+        return bench_dense(args)
 
     import torch
     import paper_2505_22631_amd as oim

@@ -24,8 +24,10 @@
  *         theta_i <- wrap(theta_i + dt f_i + sigma_t sqrt(dt) xi_{i,t}),
  *     all oscillators updated from the phases of step t (Algorithm 1).
  *   - xi_{i,t} for replica r comes from Philox4x32-10 (Salmon et al., SC'11)
- *     with key (seed_r low word, seed_r high word) and counter (i/4, t, 0, 0),
- *     t the global step index; words (x0,x1) feed oscillators i%4 = 0,1 and
+ *     with key (seed_r low word, seed_r high word) and counter (i/4, t, b, 0),
+ *     t the global step index, i the oscillator's index within its instance
+ *     and b the instance (0 unless the problem is a block-diagonal batch,
+ *     oim_problem_from_csr_blocks); words (x0,x1) feed oscillators i%4 = 0,1 and
  *     (x2,x3) feed i%4 = 2,3 through Box-Muller on 24-bit uniforms
  *     u1 = ((xa>>8)+1)/2^24, u2 = (xb>>8)/2^24: the even oscillator of a pair
  *     takes sqrt(-2 ln u1) cos(2 pi u2), the odd one the sine.
@@ -88,6 +90,18 @@ const char* oim_last_error(void);
 int oim_problem_from_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx,
                          const float* J, uint32_t flags, oim_problem* out);
 
+/* A batch of independent instances as one block-diagonal CSR: instance b
+ * holds oscillators inst_off[b] .. inst_off[b+1]-1 (inst_off[0] = 0,
+ * strictly increasing, inst_off[n_inst] = n) and no entry couples two
+ * instances (else OIM_E_CSR).  Each (instance, replica) runs as an independent
+ * solve; in-run readouts are per (replica, instance), laid out r * n_inst + b
+ * (NEXT: the ragged multi-instance batch of the colouring benchmark).  Such
+ * problems run on the LDS-resident loop only.  Other arguments and errors as
+ * for oim_problem_from_csr.  oim_problem_from_csr is the n_inst = 1 case. */
+int oim_problem_from_csr_blocks(int32_t n, int64_t nnz, const int64_t* row_ptr,
+                                const int32_t* col_idx, const float* J, int32_t n_inst,
+                                const int32_t* inst_off, uint32_t flags, oim_problem* out);
+
 /* Dense coupling J[n][n] row-major (Sec. III-B: flattened coupling matrix).
  * J must be finite and symmetric off the diagonal; the diagonal is ignored.
  * Errors as for oim_problem_from_csr.  1 <= n <= 65536.  flags must be 0. */
@@ -102,7 +116,7 @@ typedef struct {
     int32_t is_dense;          /* 1 for oim_problem_from_dense                      */
     int64_t nnz;               /* stored off-diagonal nonzeros (both triangles)     */
     int32_t integer_weights;   /* 1 if every J is an integer of magnitude < 2^24    */
-    int32_t reserved;
+    int32_t n_instances;       /* instances of a block-diagonal batch (else 1)      */
     double max_abs_row_sum;    /* max_i sum_j |J_ij| (Gershgorin bound of J)         */
     double sum_J_upper;        /* sum_{i<j} J_ij; max-cut total weight W = -this     */
 } oim_problem_info;
@@ -139,10 +153,10 @@ typedef struct {
  * phases are thresholded to colours k = floor(q * u / 2^32 + 1/2) mod q from
  * the exact phase words u, and H is evaluated: Eq. 1 (q = 2, spin s = 1 - 2k)
  * or Eq. 2 (q >= 3).
- *   trace[ceil(steps/M)][R]  H at every readout
- *   best_h[R]                lowest H seen in this call (first occurrence)
- *   best_step[R]             global step index after which best_h was seen
- *   best_colour[R][n]        colours at that readout                           */
+ *   trace[ceil(steps/M)][R*I]  H at every readout (I = instances, entry r*I+b)
+ *   best_h[R*I]                lowest H seen in this call (first occurrence)
+ *   best_step[R*I]             global step index after which best_h was seen
+ *   best_colour[R][n]          colours at that readout (per instance range)    */
 typedef struct {
     double* trace;
     double* best_h;

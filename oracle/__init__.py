@@ -38,9 +38,17 @@ def lib():
         L.orc_normal.restype = _f64
         L.orc_normals.argtypes = [_u64, _u32, _i64, _u32, _P]
         L.orc_normals.restype = None
+        L.orc_normal_b.argtypes = [_u64, _u32, _u32, _u32]
+        L.orc_normal_b.restype = _f64
+        L.orc_run_csr_blocks.argtypes = [_i32, _P, _P, _P, _i32, _P, _i32, _i32, _i32, _i64, _f64,
+                                         _P, _P, _P, _P, _P, _i32]
+        L.orc_run_csr_blocks.restype = ctypes.c_int
         L.orc_run_csr.argtypes = [_i32, _P, _P, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P,
                                   _P, _i32]
         L.orc_run_csr.restype = ctypes.c_int
+        L.orc_adjoint_csr.argtypes = [_i32, _P, _P, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P,
+                                      _P, _P, _P, _P, _P, _P]
+        L.orc_adjoint_csr.restype = ctypes.c_int
         L.orc_run_dense.argtypes = [_i32, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P, _P,
                                     _i32]
         L.orc_run_dense.restype = ctypes.c_int
@@ -79,9 +87,9 @@ def philox4x32_10(ctr, key) -> np.ndarray:
     return out
 
 
-def normal(seed: int, i: int, t: int) -> float:
-    """The standard normal that drives oscillator i at global step t."""
-    return lib().orc_normal(int(seed), int(i), int(t))
+def normal(seed: int, i: int, t: int, instance: int = 0) -> float:
+    """The standard normal that drives oscillator i (of `instance`) at global step t."""
+    return lib().orc_normal_b(int(seed), int(i), int(t), int(instance))
 
 
 def normals(seed: int, i0: int, count: int, t: int) -> np.ndarray:
@@ -116,6 +124,62 @@ def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nth
     if rc != 0:
         raise ValueError("orc_run_csr rejected its arguments")
     return th
+
+
+def run_csr_blocks(row_ptr, col, J, inst_off, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0,
+                   nthreads=0):
+    """Integrate a block-diagonal batch of instances (inst_off[b]..inst_off[b+1]-1)."""
+    rp = _c(row_ptr, np.int64)
+    cl = _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    io = _c(inst_off, np.int32)
+    th = np.array(theta0, dtype=np.float64, order="C", copy=True)
+    if th.ndim == 1:
+        th = th[None, :]
+    R, n = th.shape
+    steps = len(K)
+    sd = _c(seeds, np.uint64)
+    assert sd.shape == (R,) and rp.shape == (n + 1,) and io[-1] == n
+    rc = lib().orc_run_csr_blocks(n, _ptr(rp), _ptr(cl), _ptr(Jv), len(io) - 1, _ptr(io), int(q), R,
+                                  steps, int(step0), float(dt), _ptr(_sched(K, steps)),
+                                  _ptr(_sched(Ks, steps)), _ptr(_sched(sigma, steps)), _ptr(sd),
+                                  _ptr(th), int(nthreads))
+    if rc != 0:
+        raise ValueError("orc_run_csr_blocks rejected its arguments")
+    return th
+
+
+def adjoint_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0):
+    """Relaxed-cut loss of the final phases (sum over replicas) and its gradient with
+    respect to the per-step K, Ks and sigma of the fixed-noise trajectory."""
+    rp = _c(row_ptr, np.int64)
+    cl = _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    th = np.ascontiguousarray(np.atleast_2d(np.asarray(theta0, np.float64)))
+    R, n = th.shape
+    steps = len(K)
+    sd = _c(seeds, np.uint64)
+    loss = np.zeros(1)
+    gK, gKs, gS = np.zeros(steps), np.zeros(steps), np.zeros(steps)
+    rc = lib().orc_adjoint_csr(n, _ptr(rp), _ptr(cl), _ptr(Jv), int(q), R, steps, int(step0),
+                               float(dt), _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
+                               _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), _ptr(loss),
+                               _ptr(gK), _ptr(gKs), _ptr(gS))
+    if rc != 0:
+        raise ValueError("orc_adjoint_csr rejected its arguments")
+    return float(loss[0]), gK, gKs, gS
+
+
+def relaxed_cut(row_ptr, col, J, theta):
+    """sum over replicas of sum_{i<j} w_ij (1 - cos(th_i - th_j)) / 2, w = -J (numpy)."""
+    th = np.atleast_2d(np.asarray(theta, np.float64))
+    rp = np.asarray(row_ptr)
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    cl = np.asarray(col)
+    up = rows < cl
+    w = -np.asarray(J, np.float64)[up]
+    d = th[:, rows[up]] - th[:, cl[up]]
+    return float(np.sum(0.5 * w * (1.0 - np.cos(d))))
 
 
 def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):

@@ -26,7 +26,9 @@
  *   - Schedules K, Ks, sigma are per-step arrays indexed by the local step.
  *   - The noise is a counter-based stream: Philox4x32-10 (Salmon, Moraes, Dror,
  *     Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3", SC'11) keyed by the
- *     replica's 64-bit seed, counter (i/4, t, 0, 0), followed by Box-Muller
+ *     replica's 64-bit seed, counter (i/4, t, b, 0) with i the oscillator's
+ *     index within its instance and b the instance of a block-diagonal batch
+ *     (a single graph is instance 0), followed by Box-Muller
  *     (Box & Muller 1958) on 24-bit uniforms.  Words (x0,x1) serve oscillators
  *     i = 0,1 mod 4 and (x2,x3) serve i = 2,3 mod 4; the even member of a pair
  *     takes rho*cos(2 pi u2), the odd one rho*sin(2 pi u2).
@@ -73,10 +75,10 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     memcpy(out, x, sizeof x);
 }
 
-/* One standard normal for oscillator i at global step t of the replica whose
- * seed is `seed`. */
-double orc_normal(uint64_t seed, uint32_t i, uint32_t t) {
-    const uint32_t ctr[4] = {i >> 2, t, 0u, 0u};
+/* One standard normal for oscillator i (index within instance b) at global
+ * step t of the replica whose seed is `seed`. */
+double orc_normal_b(uint64_t seed, uint32_t i, uint32_t t, uint32_t b) {
+    const uint32_t ctr[4] = {i >> 2, t, b, 0u};
     const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t x[4];
     orc_philox4x32_10(ctr, key, x);
@@ -87,6 +89,8 @@ double orc_normal(uint64_t seed, uint32_t i, uint32_t t) {
     const double rho = sqrt(-2.0 * log(u1));
     return (i & 1u) ? rho * sin(ORC_TWO_PI * u2) : rho * cos(ORC_TWO_PI * u2);
 }
+
+double orc_normal(uint64_t seed, uint32_t i, uint32_t t) { return orc_normal_b(seed, i, t, 0u); }
 
 void orc_normals(uint64_t seed, uint32_t i0, int64_t count, uint32_t t, double* out) {
     for (int64_t k = 0; k < count; ++k) out[k] = orc_normal(seed, (uint32_t)(i0 + k), t);
@@ -106,8 +110,21 @@ static double wrap_2pi(double th) {
 static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* Jv,
                       const double* Jdense, int32_t q, int32_t R, int32_t steps, int64_t step0,
                       double dt, const double* K, const double* Ks, const double* sigma,
-                      const uint64_t* seeds, double* theta, int32_t nthreads) {
+                      const uint64_t* seeds, double* theta, int32_t nthreads, int32_t n_inst,
+                      const int32_t* inst_off) {
     if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0)) return -1;
+    /* instance of every oscillator and its index within the instance */
+    uint32_t* inst_of = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    uint32_t* local = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
+    if (!inst_of || !local) { free(inst_of); free(local); return -1; }
+    for (int32_t i = 0; i < n; ++i) { inst_of[i] = 0; local[i] = (uint32_t)i; }
+    if (inst_off && n_inst > 1) {
+        for (int32_t b = 0; b < n_inst; ++b)
+            for (int32_t i = inst_off[b]; i < inst_off[b + 1]; ++i) {
+                inst_of[i] = (uint32_t)b;
+                local[i] = (uint32_t)(i - inst_off[b]);
+            }
+    }
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #else
@@ -137,12 +154,14 @@ static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, con
             const double sq = sqrt(dt);
             for (int32_t i = 0; i < n; ++i) {
                 const double f = -K[s] * coup[i] - Ks[s] * sin((double)q * th[i]);
-                const double xi = orc_normal(seeds[r], (uint32_t)i, t);
+                const double xi = orc_normal_b(seeds[r], local[i], t, inst_of[i]);
                 th[i] = wrap_2pi(th[i] + dt * f + sigma[s] * sq * xi);
             }
         }
         free(coup);
     }
+    free(inst_of);
+    free(local);
     return bad ? -1 : 0;
 }
 
@@ -151,14 +170,26 @@ int orc_run_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const dou
                 const double* Ks, const double* sigma, const uint64_t* seeds, double* theta,
                 int32_t nthreads) {
     return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
-                      theta, nthreads);
+                      theta, nthreads, 1, NULL);
+}
+
+/* Block-diagonal batch: instance b holds oscillators inst_off[b] .. inst_off[b+1]-1
+ * (no coupling between instances); the noise of each oscillator is drawn with its
+ * index within its instance and the instance number. */
+int orc_run_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                       int32_t n_inst, const int32_t* inst_off, int32_t q, int32_t R,
+                       int32_t steps, int64_t step0, double dt, const double* K, const double* Ks,
+                       const double* sigma, const uint64_t* seeds, double* theta,
+                       int32_t nthreads) {
+    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+                      theta, nthreads, n_inst, inst_off);
 }
 
 int orc_run_dense(int32_t n, const double* J, int32_t q, int32_t R, int32_t steps, int64_t step0,
                   double dt, const double* K, const double* Ks, const double* sigma,
                   const uint64_t* seeds, double* theta, int32_t nthreads) {
     return run_common(n, NULL, NULL, NULL, J, q, R, steps, step0, dt, K, Ks, sigma, seeds, theta,
-                      nthreads);
+                      nthreads, 1, NULL);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -246,3 +277,82 @@ double orc_h_eq6(int32_t n, const int64_t* row_ptr, const int32_t* col, const do
 }
 
 int orc_abi_version(void) { return 1; }
+
+/* ------------------------------------------------------------------------ */
+/* Adjoint of the fixed-noise Euler-Maruyama trajectory (schedule tuning).   */
+/*   loss      L = sum_r sum_{i<j} w_ij (1 - cos(th_T,i - th_T,j)) / 2,      */
+/*             w = -J  (the relaxed cut at the final phases)                 */
+/*   lam_T,i   = dL/dth_T,i = 1/2 sum_j w_ij sin(th_i - th_j)                */
+/*   step      th_{t+1} = th_t + dt f(th_t) + sigma_t sqrt(dt) xi_t,         */
+/*             f_i = -K_t sum_j J_ij sin(th_i - th_j) - Ks_t sin(q th_i)     */
+/*   lam_t,k   = lam_{t+1,k} + dt sum_i lam_{t+1,i} df_i/dth_k                */
+/*             = lam_{t+1,k} + dt [ K_t sum_j J_kj cos(th_k - th_j)          */
+/*                 (lam_{t+1,j} - lam_{t+1,k}) - q Ks_t cos(q th_k) lam_{t+1,k} ] */
+/*   dL/dK_t   = -dt sum lam_{t+1,i} sum_j J_ij sin(th_t,i - th_t,j)          */
+/*   dL/dKs_t  = -dt sum lam_{t+1,i} sin(q th_t,i)                           */
+/*   dL/dsig_t = sqrt(dt) sum lam_{t+1,i} xi_t,i                             */
+/* The wrap into one period has derivative 1 almost everywhere.  All sums    */
+/* run over replicas too (one schedule drives every replica).                */
+/* ------------------------------------------------------------------------ */
+int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                    int32_t q, int32_t R, int32_t steps, int64_t step0, double dt,
+                    const double* K, const double* Ks, const double* sigma,
+                    const uint64_t* seeds, const double* theta0, double* loss, double* gK,
+                    double* gKs, double* gS) {
+    if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0)) return -1;
+    const size_t N = (size_t)n;
+    double* traj = (double*)malloc(sizeof(double) * N * (size_t)(steps + 1));
+    double* lam = (double*)malloc(sizeof(double) * N);
+    double* nxt = (double*)malloc(sizeof(double) * N);
+    if (!traj || !lam || !nxt) { free(traj); free(lam); free(nxt); return -1; }
+    for (int32_t s = 0; s < steps; ++s) gK[s] = gKs[s] = gS[s] = 0.0;
+    double total = 0.0;
+    const double sq = sqrt(dt);
+    for (int32_t r = 0; r < R; ++r) {
+        /* forward, keeping every state */
+        memcpy(traj, theta0 + (size_t)r * N, sizeof(double) * N);
+        if (run_common(n, row_ptr, col, J, NULL, q, 1, 0, step0, dt, K, Ks, sigma, seeds + r,
+                       traj, 1, 1, NULL) != 0) { total = NAN; break; }
+        for (int32_t s = 0; s < steps; ++s) {
+            memcpy(traj + N * (s + 1), traj + N * s, sizeof(double) * N);
+            if (run_common(n, row_ptr, col, J, NULL, q, 1, 1, step0 + s, dt, K + s, Ks + s,
+                           sigma + s, seeds + r, traj + N * (s + 1), 1, 1, NULL) != 0) {
+                total = NAN;
+                break;
+            }
+        }
+        const double* thT = traj + N * (size_t)steps;
+        for (int32_t i = 0; i < n; ++i) {
+            double g = 0.0;
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                const int32_t j = col[e];
+                const double w = -J[e];
+                g += 0.5 * w * sin(thT[i] - thT[j]);
+                if (i < j) total += 0.5 * w * (1.0 - cos(thT[i] - thT[j]));
+            }
+            lam[i] = g;
+        }
+        for (int32_t s = steps - 1; s >= 0; --s) {
+            const double* th = traj + N * (size_t)s;
+            const uint32_t t = (uint32_t)(step0 + s);
+            for (int32_t k = 0; k < n; ++k) {
+                double cc = 0.0, csin = 0.0;
+                for (int64_t e = row_ptr[k]; e < row_ptr[k + 1]; ++e) {
+                    const int32_t j = col[e];
+                    cc += J[e] * cos(th[k] - th[j]) * (lam[j] - lam[k]);
+                    csin += J[e] * sin(th[k] - th[j]);
+                }
+                nxt[k] = lam[k] + dt * (K[s] * cc - (double)q * Ks[s] * cos((double)q * th[k]) * lam[k]);
+                gK[s] += -dt * lam[k] * csin;
+                gKs[s] += -dt * lam[k] * sin((double)q * th[k]);
+                gS[s] += sq * lam[k] * orc_normal(seeds[r], (uint32_t)k, t);
+            }
+            memcpy(lam, nxt, sizeof(double) * N);
+        }
+    }
+    *loss = total;
+    free(traj);
+    free(lam);
+    free(nxt);
+    return 0;
+}

@@ -23,7 +23,7 @@ from ._lib import (OIM_LOOP_AUTO, OIM_LOOP_PERSISTENT, OIM_LOOP_STEPWISE, OIM_PR
 __all__ = [
     "OIM_LOOP_AUTO", "OIM_LOOP_PERSISTENT", "OIM_LOOP_STEPWISE", "OIM_PREC_FP32",
     "OIM_PREC_BF16X3", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
-    "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
+    "oim_problem_from_csr_blocks", "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
     "oim_round", "oim_cut", "oim_conflicts", "oim_energy", "oim_phase_from_theta",
     "oim_theta_from_phase", "run", "n_readouts",
 ]
@@ -78,6 +78,23 @@ def oim_problem_from_csr(n, row_ptr, col_idx, J, flags=0):
     return h
 
 
+def oim_problem_from_csr_blocks(n, row_ptr, col_idx, J, inst_off, flags=0):
+    """Upload a block-diagonal batch: instance b = oscillators inst_off[b]..inst_off[b+1]-1."""
+    rp = _host(row_ptr, np.int64)
+    ci = _host(col_idx, np.int32)
+    Jv = _host(J, np.float32)
+    io = _host(inst_off, np.int32)
+    if rp.shape != (int(n) + 1,):
+        raise ValueError("row_ptr must have n+1 entries")
+    if ci.shape != Jv.shape:
+        raise ValueError("col_idx and J must have the same length")
+    h = ctypes.c_void_p()
+    check(lib().oim_problem_from_csr_blocks(int(n), int(ci.size), _np_ptr(rp), _np_ptr(ci),
+                                            _np_ptr(Jv), int(io.size - 1), _np_ptr(io),
+                                            int(flags), ctypes.byref(h)))
+    return h
+
+
 def oim_problem_from_dense(J, flags=0):
     """Upload a dense symmetric coupling J[n][n] (host array, copied)."""
     Jd = _host(J, np.float32)
@@ -96,7 +113,7 @@ def oim_problem_destroy(h) -> None:
 def oim_problem_info_get(h) -> dict:
     info = _lib.ProblemInfo()
     check(lib().oim_problem_info_get(h, ctypes.byref(info)))
-    return {k: getattr(info, k) for k, _ in _lib.ProblemInfo._fields_ if k != "reserved"}
+    return {k: getattr(info, k) for k, _ in _lib.ProblemInfo._fields_}
 
 
 def n_readouts(steps: int, readout_every: int) -> int:
@@ -115,9 +132,10 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
     steps = int(K.shape[0])
     cfg = RunCfg(int(q), R, steps, float(dt), int(readout_every), int(flags))
     nr = n_readouts(steps, readout_every)
-    ro = Readout(_dev(trace, torch.float64, (nr, R), "trace", True),
-                 _dev(best_h, torch.float64, (R,), "best_h", True),
-                 _dev(best_step, torch.int32, (R,), "best_step", True),
+    RI = R * int(oim_problem_info_get(h)["n_instances"])
+    ro = Readout(_dev(trace, torch.float64, (nr, RI), "trace", True),
+                 _dev(best_h, torch.float64, (RI,), "best_h", True),
+                 _dev(best_step, torch.int32, (RI,), "best_step", True),
                  _dev(best_colour, torch.int8, (R, n), "best_colour", True))
     check(lib().oim_run(h, ctypes.byref(cfg), _dev(K, torch.float32, (steps,), "K"),
                         _dev(Ks, torch.float32, (steps,), "Ks"),
@@ -203,6 +221,10 @@ class Problem:
         return cls(oim_problem_from_csr(n, row_ptr, col_idx, J), n)
 
     @classmethod
+    def from_csr_blocks(cls, n, row_ptr, col_idx, J, inst_off):
+        return cls(oim_problem_from_csr_blocks(n, row_ptr, col_idx, J, inst_off), n)
+
+    @classmethod
     def from_dense(cls, J):
         return cls(oim_problem_from_dense(J), np.asarray(J).shape[0])
 
@@ -232,10 +254,11 @@ def run(problem: Problem, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0,
     out = {}
     if readout_every > 0:
         dev = theta.device
-        out["trace"] = torch.empty((n_readouts(steps, readout_every), R), dtype=torch.float64,
+        RI = R * int(problem.info["n_instances"])
+        out["trace"] = torch.empty((n_readouts(steps, readout_every), RI), dtype=torch.float64,
                                    device=dev)
-        out["best_h"] = torch.empty(R, dtype=torch.float64, device=dev)
-        out["best_step"] = torch.empty(R, dtype=torch.int32, device=dev)
+        out["best_h"] = torch.empty(RI, dtype=torch.float64, device=dev)
+        out["best_step"] = torch.empty(RI, dtype=torch.int32, device=dev)
         if want_best:
             out["best_colour"] = torch.empty((R, n), dtype=torch.int8, device=dev)
     oim_run(problem.handle, problem.n, theta, K, Ks, sigma, seeds, q=q, dt=dt,

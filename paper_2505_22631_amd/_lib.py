@@ -29,7 +29,7 @@ class Readout(ctypes.Structure):
 
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", _i32), ("is_dense", _i32), ("nnz", _i64), ("integer_weights", _i32),
-                ("reserved", _i32), ("max_abs_row_sum", ctypes.c_double),
+                ("n_instances", _i32), ("max_abs_row_sum", ctypes.c_double),
                 ("sum_J_upper", ctypes.c_double)]
 
 
@@ -39,6 +39,8 @@ PROTOTYPES = {
     "oim_status_str": (ctypes.c_char_p, [ctypes.c_int]),
     "oim_last_error": (ctypes.c_char_p, []),
     "oim_problem_from_csr": (ctypes.c_int, [_i32, _i64, _P, _P, _P, _u32, ctypes.POINTER(_P)]),
+    "oim_problem_from_csr_blocks": (ctypes.c_int, [_i32, _i64, _P, _P, _P, _i32, _P, _u32,
+                                                   ctypes.POINTER(_P)]),
     "oim_problem_from_dense": (ctypes.c_int, [_i32, _P, _u32, ctypes.POINTER(_P)]),
     "oim_problem_destroy": (None, [_P]),
     "oim_problem_info_get": (ctypes.c_int, [_P, ctypes.POINTER(ProblemInfo)]),

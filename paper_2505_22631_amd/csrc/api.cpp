@@ -38,6 +38,8 @@ void release(Problem* p) {
     hipFree(p->d_J);
     hipFree(p->d_sell_desc);
     hipFree(p->d_sell);
+    hipFree(p->d_inst);
+    hipFree(p->d_order);
     hipFree(p->d_work);
     dense_release(p);
     p->magic = kDeadMagic;
@@ -101,35 +103,46 @@ __attribute__((visibility("default"))) const char* oim_last_error(void) {
     return last_error_cstr();
 }
 
-__attribute__((visibility("default"))) int oim_problem_from_csr(
+__attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
-    uint32_t flags, oim_problem* out) {
+    int32_t n_inst, const int32_t* inst_off, uint32_t flags, oim_problem* out) {
     clear_error();
     if (!out) return set_error(OIM_E_ARG, "out is NULL");
     *out = nullptr;
     if (flags != 0) return set_error(OIM_E_ARG, "flags must be 0");
     int st = validate_csr(n, nnz, row_ptr, col_idx, J);
     if (st) return st;
+    if ((st = validate_blocks(n, row_ptr, col_idx, n_inst, inst_off))) return st;
     Problem* p = new (std::nothrow) Problem();
     if (!p) return set_error(OIM_E_NOMEM, "host allocation failed");
     p->n = n;
     p->nnz = nnz;
+    p->n_inst = n_inst;
     weight_stats(p, n, row_ptr, col_idx, J);
     SellImage img;
-    build_sell(n, row_ptr, col_idx, J, img);
+    build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img);
     p->sell_slices = img.slices;
+    p->max_slices = img.max_slices;
     p->sell_entries = (int64_t)img.entries.size();
     if ((st = current_device(&p->device)) ||
         (st = dev_upload(&p->d_row_ptr, row_ptr, (size_t)n + 1, "upload row_ptr")) ||
         (st = dev_upload(&p->d_col, col_idx, (size_t)nnz, "upload col_idx")) ||
         (st = dev_upload(&p->d_J, J, (size_t)nnz, "upload J")) ||
         (st = dev_upload(&p->d_sell_desc, img.desc.data(), img.desc.size(), "upload slices")) ||
-        (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell"))) {
+        (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell")) ||
+        (st = dev_upload(&p->d_inst, img.inst.data(), img.inst.size(), "upload instances")) ||
+        (st = dev_upload(&p->d_order, img.order.data(), img.order.size(), "upload order"))) {
         release(p);
         return st;
     }
     *out = reinterpret_cast<oim_problem>(p);
     return OIM_OK;
+}
+
+__attribute__((visibility("default"))) int oim_problem_from_csr(
+    int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+    uint32_t flags, oim_problem* out) {
+    return oim_problem_from_csr_blocks(n, nnz, row_ptr, col_idx, J, 1, nullptr, flags, out);
 }
 
 __attribute__((visibility("default"))) int oim_problem_from_dense(int32_t n, const float* J,
@@ -191,6 +204,7 @@ __attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
     info->is_dense = p->dense ? 1 : 0;
     info->nnz = p->nnz;
     info->integer_weights = p->integer_weights ? 1 : 0;
+    info->n_instances = p->n_inst;
     info->max_abs_row_sum = p->max_abs_row_sum;
     info->sum_J_upper = p->sum_J_upper;
     return OIM_OK;
@@ -222,6 +236,8 @@ __attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_
         return launch_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
     }
     const bool fits = persistent_sparse_fits(p);
+    if (p->n_inst > 1 && (loop == OIM_LOOP_STEPWISE || !fits))
+        return set_error(OIM_E_UNSUPPORTED, "block-diagonal batches run on the LDS-resident loop only");
     if (loop == OIM_LOOP_PERSISTENT || (loop == OIM_LOOP_AUTO && fits))
         return launch_persistent_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro,
                                         stream);

@@ -34,7 +34,10 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kTM = 128;  // rows per workgroup
 constexpr int kTR = 64;   // replicas per workgroup
-constexpr int kTK = 32;   // K per stage
+constexpr int kTK = 32;   // K per stage (one MFMA K-step)
+constexpr int kDepth = 4; // LDS stage buffers (kDepth - 1 stages of loads in flight)
+constexpr int kSegs = kTK / 8;                            // 16-byte segments per LDS row
+constexpr int kStageBytes = (2 * kTM + 4 * kTR) * kTK * 2;  // A hi/lo + B 4 comps
 constexpr int kTB = 256;  // threads
 
 __device__ __forceinline__ uint16_t bf16_bits(float x) {
@@ -50,9 +53,12 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
     lo = bf16_bits(x - bf16_val(hi));
 }
 
-// 16-byte segment index within a 64-byte LDS row, XOR-swizzled by row so the
-// 16 rows x 4 segments a wave reads per fragment hit every bank once.
-__device__ __forceinline__ int swz(int row, int seg) { return row * 64 + ((seg ^ ((row >> 1) & 3)) << 4); }
+// Byte offset of 16-byte segment `seg` of LDS row `row` (rows of kTK bf16 =
+// 64 bytes), XOR-swizzled by row so that the 8 consecutive rows a group of
+// lanes reads at one logical segment cover all banks once.
+__device__ __forceinline__ int swz(int row, int seg) {
+    return row * (kTK * 2) + ((seg ^ ((row >> 1) & (kSegs - 1))) << 4);
+}
 
 struct DenseArgs {
     const uint16_t* Jhi;   // [np][np]
@@ -71,47 +77,68 @@ struct DenseArgs {
     float dt, sqrt_dt;
 };
 
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void glb_void_t;
+
+constexpr int kRow = kTK * 2;              // bytes per LDS row
+constexpr int kA = kTM * kRow;             // one A matrix per stage
+constexpr int kB = kTR * kRow;             // one B component per stage
+constexpr int kWaveChunks = kStageBytes / 1024 / (kTB / 64);  // 1 KiB DMA chunks per wave per stage
+
+// s_waitcnt immediate that waits until at most `n` vector-memory operations
+// of this wave are outstanding (lgkm and exp counters left at their maxima).
+__device__ __forceinline__ constexpr int vmcnt_imm(int n) {
+    return (n & 0xf) | ((n >> 4) << 14) | (0x7 << 4) | (0xf << 8);
+}
+
+// Barrier that completes this wave's LDS reads and nothing else: the DMA
+// loads of later stages stay in flight (a workgroup fence, as in
+// __syncthreads, would wait for every outstanding vector-memory operation).
+// The memory clobber keeps the compiler from moving LDS accesses across it.
+__device__ __forceinline__ void lds_barrier() {
+    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
+// One 256-thread workgroup per CU (one wave per SIMD).  Stages move from
+// global memory to LDS with direct DMA loads (global_load_lds_dwordx4: lane
+// l of a wave writes bytes 16l..16l+15 of a 1 KiB LDS chunk), so no staging
+// registers are needed and kDepth - 1 stages are in flight while one is
+// multiplied.  The XOR swizzle of the LDS rows is applied on the source
+// side: lane l fetches the segment that belongs at its fixed LDS slot.
 template <int QM>
-__global__ __launch_bounds__(kTB) void dense_step_kernel(DenseArgs a) {
-    __shared__ __align__(16) unsigned char lds[2][(2 * kTM + 4 * kTR) * 64];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void dense_step_kernel(DenseArgs a) {
+    __shared__ __align__(1024) unsigned char lds[kDepth][kStageBytes];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int i0 = blockIdx.x * kTM, r0 = blockIdx.y * kTR;
     const int np = a.np, Rp = a.Rp;
     const size_t plane = (size_t)Rp * np;
 
-    // global -> LDS staging: 16-byte chunks; A: 2 matrices x 128 rows x 4 segs
-    // (2 per thread each), B: 4 comps x 64 replicas x 4 segs (4 per thread)
-    auto load_stage = [&](int k0, uint4 (&ra)[4], uint4 (&rb)[4]) {
+    // Chunk c of a stage (16 rows x 64 bytes) sits at LDS bytes 1024c: chunks
+    // 0-7 are J_hi rows, 8-15 J_lo rows, 16-31 the four X components (4 chunks
+    // each).  Wave w moves chunks 8w..8w+7; lane l lands on row l/4 of the
+    // chunk, slot l%4, which holds logical segment (l%4) ^ ((row>>1)&3).
+    const int lrow = lane >> 2, lseg = (lane & 3) ^ ((lrow >> 1) & (kSegs - 1));
+    const uint16_t* src[kWaveChunks];
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int c = tid + x * kTB;          // 0..1023
-            const int mat = c >> 9, row = (c >> 2) & 127, seg = c & 3;
-            const uint16_t* src = (mat ? a.Jlo : a.Jhi) + (size_t)(i0 + row) * np + k0 + seg * 8;
-            ra[x] = *reinterpret_cast<const uint4*>(src);
+    for (int x = 0; x < kWaveChunks; ++x) {
+        const int c = wave * kWaveChunks + x;
+        if (c < 16) {
+            const int row = (c & 7) * 16 + lrow;
+            src[x] = (c < 8 ? a.Jhi : a.Jlo) + (size_t)(i0 + row) * np + lseg * 8;
+        } else {
+            const int comp = (c - 16) >> 2, row = ((c - 16) & 3) * 16 + lrow;
+            src[x] = a.Xin + comp * plane + (size_t)(r0 + row) * np + lseg * 8;
         }
+    }
+    auto issue = [&](int kc) __attribute__((always_inline)) {
+        unsigned char* dst = lds[kc % kDepth] + wave * kWaveChunks * 1024;
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int c = tid + x * kTB;          // 0..1023
-            const int comp = c >> 8, row = (c >> 2) & 63, seg = c & 3;
-            const uint16_t* src = a.Xin + comp * plane + (size_t)(r0 + row) * np + k0 + seg * 8;
-            rb[x] = *reinterpret_cast<const uint4*>(src);
-        }
-    };
-    auto store_stage = [&](int buf, const uint4 (&ra)[4], const uint4 (&rb)[4]) {
-        unsigned char* base = lds[buf];
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int c = tid + x * kTB;
-            const int mat = c >> 9, row = (c >> 2) & 127, seg = c & 3;
-            *reinterpret_cast<uint4*>(base + mat * kTM * 64 + swz(row, seg)) = ra[x];
-        }
-#pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int c = tid + x * kTB;
-            const int comp = c >> 8, row = (c >> 2) & 63, seg = c & 3;
-            *reinterpret_cast<uint4*>(base + 2 * kTM * 64 + comp * kTR * 64 + swz(row, seg)) = rb[x];
-        }
+        for (int x = 0; x < kWaveChunks; ++x)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(src[x] + (size_t)kc * kTK),
+                                             (lds_void_t*)(dst + x * 1024), 16, 0, 0);
     };
 
     f32x4 acc[4][2][2];  // [row block][replica block][S, C]
@@ -120,32 +147,38 @@ __global__ __launch_bounds__(kTB) void dense_step_kernel(DenseArgs a) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[b][c][0] = acc[b][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    uint4 ra[4], rb[4];
-    load_stage(0, ra, rb);
-    store_stage(0, ra, rb);
-    __syncthreads();
-    const int nk = np / kTK;
+    const int nk = np / kTK;  // at least kDepth (np is a multiple of 128)
+    const int frow = lane & 15, fseg = lane >> 4;
+#pragma unroll
+    for (int d = 0; d < kDepth - 1; ++d) issue(d);
     for (int kc = 0; kc < nk; ++kc) {
-        const int buf = kc & 1;
-        if (kc + 1 < nk) load_stage((kc + 1) * kTK, ra, rb);
-        const unsigned char* base = lds[buf];
-        const int frow = lane & 15, fseg = lane >> 4;
+        // stage kc has landed once at most (stages issued after it) x chunks
+        // of this wave's DMA loads are outstanding
+        const int ahead = nk - 1 - kc < kDepth - 2 ? nk - 1 - kc : kDepth - 2;
+        if (ahead == kDepth - 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 2) * kWaveChunks));
+        else if (ahead == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(kWaveChunks));
+        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+        // all waves' chunks of stage kc are in LDS, and every wave is done
+        // reading the buffer that stage kc + kDepth - 1 overwrites
+        lds_barrier();
+        if (kc + kDepth - 1 < nk) issue(kc + kDepth - 1);
+        const unsigned char* base = lds[kc % kDepth];
         bf16x8 bh[2][2], bl[2][2];  // [replica block][S, C]
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int row = wn * 32 + cb * 16 + frow;
 #pragma unroll
             for (int sc = 0; sc < 2; ++sc) {
-                const unsigned char* bb = base + 2 * kTM * 64 + (2 * sc) * kTR * 64;
+                const unsigned char* bb = base + 2 * kA + (2 * sc) * kB;
                 bh[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + swz(row, fseg));
-                bl[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + kTR * 64 + swz(row, fseg));
+                bl[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + kB + swz(row, fseg));
             }
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int row = wm * 64 + b * 16 + frow;
             const bf16x8 ah = *reinterpret_cast<const bf16x8*>(base + swz(row, fseg));
-            const bf16x8 al = *reinterpret_cast<const bf16x8*>(base + kTM * 64 + swz(row, fseg));
+            const bf16x8 al = *reinterpret_cast<const bf16x8*>(base + kA + swz(row, fseg));
 #pragma unroll
             for (int cb = 0; cb < 2; ++cb) {
 #pragma unroll
@@ -158,8 +191,6 @@ __global__ __launch_bounds__(kTB) void dense_step_kernel(DenseArgs a) {
                 }
             }
         }
-        if (kc + 1 < nk) store_stage(buf ^ 1, ra, rb);
-        __syncthreads();
     }
 
     // ---- epilogue: SHIL, noise, Euler-Maruyama update, next split X ----
@@ -177,7 +208,7 @@ __global__ __launch_bounds__(kTB) void dense_step_kernel(DenseArgs a) {
             uint4 u4 = *reinterpret_cast<const uint4*>(a.U + (size_t)r * np + i);
             uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
             float z[4];
-            normals4((uint32_t)(i >> 2), a.t, k0, k1, z);
+            normals4((uint32_t)(i >> 2), a.t, 0u, k0, k1, z);
             uint16_t shi[4], slo[4], chi[4], clo[4];
 #pragma unroll
             for (int x = 0; x < 4; ++x) {
@@ -324,7 +355,7 @@ int check_launch(const char* what) {
 
 int dense_prepare(Problem* p, const float* J) {
     const int n = p->n;
-    const int np = (n + kTM - 1) / kTM * kTM;
+    const int np = (n + kTM - 1) / kTM * kTM;  // also a multiple of kTK
     const size_t bytes = (size_t)n * n * sizeof(float);
     int st;
     if ((st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jdense), bytes, "dense J"))) return st;

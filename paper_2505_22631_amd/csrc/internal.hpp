@@ -26,10 +26,15 @@ constexpr int kSliceQuads = 64;  // quads (4 oscillators) per slice = one wave's
 // Padding entries carry J = 0 and point at a valid row.  Oscillator i lives
 // at LDS slot (i % 4) * (64 * slices) + i / 4 (four planes, one per quad
 // member) so the lanes of a wave touch consecutive (sin, cos) pairs.
+// A block-diagonal batch gets one image per instance, concatenated: each
+// instance starts on a slice boundary and its LDS offsets are local.
 struct SellImage {
     int32_t slices = 0;
     std::vector<int2> desc;      // [slices]: (base_s in int4 rows, deg_s)
     std::vector<int2> entries;   // [sum_s 4 * deg_s * 64]
+    std::vector<int4> inst;      // [instances]: (first slice, slices, first oscillator, n_b)
+    std::vector<int32_t> order;  // instances, most slices first
+    int32_t max_slices = 0;
 };
 
 struct Problem {
@@ -46,6 +51,12 @@ struct Problem {
     int64_t* d_row_ptr = nullptr;
     int32_t* d_col = nullptr;
     float* d_J = nullptr;
+
+    // instances of a block-diagonal batch (1 for a single graph)
+    int32_t n_inst = 1;
+    int4* d_inst = nullptr;
+    int32_t* d_order = nullptr;
+    int32_t max_slices = 0;
 
     // device: sliced-ELL image for the LDS-resident step kernel
     int32_t sell_slices = 0;
@@ -74,8 +85,10 @@ int validate_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* 
 int validate_dense(int32_t n, const float* J);
 int validate_cfg(const Problem* p, const oim_run_cfg* cfg);
 Problem* checked(oim_problem p);
+int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t n_inst,
+                    const int32_t* inst_off);
 void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
-                SellImage& out);
+                int32_t n_inst, const int32_t* inst_off, SellImage& out);
 
 // kernels' host launchers
 int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,

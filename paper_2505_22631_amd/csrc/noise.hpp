@@ -8,7 +8,9 @@
 //   per round, multipliers 0xD2511F53 / 0xCD9E8D57, Weyl key increments
 //   0x9E3779B9 / 0xBB67AE85, ten rounds.
 //   key     = (seed & 0xffffffff, seed >> 32)
-//   counter = (i >> 2, t, 0, 0)      t = global step index
+//   counter = (i >> 2, t, b, 0)      t = global step index, i the oscillator's
+//                                    index within its instance, b the instance
+//                                    of a block-diagonal batch (0 otherwise)
 //   one call gives the normals of oscillators 4m..4m+3 via Box-Muller
 //   (Box & Muller 1958) on the word pairs (x0,x1) and (x2,x3):
 //   u1 = ((xa >> 8) + 1) * 2^-24 in (0,1], u2 = (xb >> 8) * 2^-24 in [0,1),
@@ -55,10 +57,11 @@ __device__ __forceinline__ void box_muller(uint32_t xa, uint32_t xb, float& z_ev
     z_odd = rho * __builtin_amdgcn_sinf(u2);
 }
 
-// The four normals of oscillators 4m..4m+3 at step t for a replica key.
-__device__ __forceinline__ void normals4(uint32_t m, uint32_t t, uint32_t k0, uint32_t k1,
-                                         float z[4]) {
-    const u32x4 x = philox4x32_10(u32x4{m, t, 0u, 0u}, k0, k1);
+// The four normals of oscillators 4m..4m+3 of instance b at step t for a
+// replica key.
+__device__ __forceinline__ void normals4(uint32_t m, uint32_t t, uint32_t b, uint32_t k0,
+                                         uint32_t k1, float z[4]) {
+    const u32x4 x = philox4x32_10(u32x4{m, t, b, 0u}, k0, k1);
     box_muller(x.x, x.y, z[0], z[1]);
     box_muller(x.z, x.w, z[2], z[3]);
 }

@@ -35,10 +35,11 @@ namespace {
 struct PersistArgs {
     const int4* sell;   // sliced-ELL entries, two per int4 (see SellImage)
     const int2* desc;   // per slice: (base in int4 rows, padded degree)
+    const int4* inst;   // per instance: (first slice, slices, first oscillator, oscillators)
+    const int32_t* order;  // instances, most slices first
+    int32_t I;          // instances
+    int32_t n_total;    // oscillators of all instances (row length of theta)
     uint32_t sell_bytes;
-    int32_t S;          // slices
-    int32_t plane;      // S * 64: length of one LDS plane
-    int32_t n;
     int32_t q;
     int32_t steps;
     int32_t M;          // readout period (0 = none)
@@ -48,12 +49,12 @@ struct PersistArgs {
     const float* Ks;
     const float* sigma;
     const uint64_t* seeds;
-    float* theta;       // [R][n]
-    uint32_t* phase;    // [R][n] or null
-    double* trace;      // [ceil(steps/M)][R]
-    double* best_h;     // [R]
-    int32_t* best_step;
-    int8_t* best_colour;  // [R][n]
+    float* theta;       // [R][n_total]
+    uint32_t* phase;    // [R][n_total] or null
+    double* trace;      // [ceil(steps/M)][R][I]
+    double* best_h;     // [R][I]
+    int32_t* best_step; // [R][I]
+    int8_t* best_colour;  // [R][n_total]
     int32_t R;
 };
 
@@ -68,21 +69,26 @@ __device__ __forceinline__ float2 sc_at(const unsigned char* smem, int byte_off)
 template <int TB, int MS, int QM>
 __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
+    // workgroup -> (instance, replica): all replicas of the largest instance first
+    const int inst_id = a.order[blockIdx.x / a.R];
+    const int r = blockIdx.x % a.R;
+    const int4 idesc = a.inst[inst_id];
+    const int slice0 = idesc.x, S = idesc.y, off = idesc.z, n = idesc.w;
+    const int plane = S * 64;
     float2* sc = reinterpret_cast<float2*>(smem);                   // [4 * plane]
-    unsigned char* col8 = smem + (size_t)8 * 4 * a.plane;          // [4 * plane] (readout)
-    double* red = reinterpret_cast<double*>(col8 + ((4 * a.plane + 15) & ~15));  // [W]
+    unsigned char* col8 = smem + (size_t)8 * 4 * plane;            // [4 * plane] (readout)
+    double* red = reinterpret_cast<double*>(col8 + ((4 * plane + 15) & ~15));  // [W]
     int* flag = reinterpret_cast<int*>(red + TB / 64);
 
     constexpr int W = TB / 64;
-    const int r = blockIdx.x;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int n = a.n, plane = a.plane, S = a.S;
     const int q = QM ? QM : a.q;
     const uint64_t seed = a.seeds[r];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-    float* th = a.theta + (int64_t)r * n;
-    uint32_t* pw = a.phase ? a.phase + (int64_t)r * n : nullptr;
+    float* th = a.theta + (int64_t)r * a.n_total + off;
+    uint32_t* pw = a.phase ? a.phase + (int64_t)r * a.n_total + off : nullptr;
+    const int out_id = r * a.I + inst_id;
     const __amdgpu_buffer_rsrc_t rsrc =
         __builtin_amdgcn_make_buffer_rsrc((void*)a.sell, (short)0, (int)a.sell_bytes, 0x00020000);
     const int voff = lane * 16;
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
         const int slice = wave + k * W;
-        const int2 d = slice < S ? a.desc[slice] : make_int2(0, 0);
+        const int2 d = slice < S ? a.desc[slice0 + slice] : make_int2(0, 0);
         sbase[k] = __builtin_amdgcn_readfirstlane(d.x);
         sdeg[k] = __builtin_amdgcn_readfirstlane(d.y);
         const int m = slice * 64 + lane;
@@ -175,7 +181,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 uint32_t mm = (uint32_t)m, kk0 = k0, kk1 = k1;
                 asm volatile("" : "+v"(mm), "+s"(kk0), "+s"(kk1));
                 float z[4];
-                normals4(mm, t, kk0, kk1, z);
+                normals4(mm, t, (uint32_t)inst_id, kk0, kk1, z);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const uint32_t u = advance(ph[k][j], __builtin_fmaf(ns, z[j], drift[k][j]));
@@ -233,7 +239,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 for (int w = 0; w < W; ++w) tot += red[w];
                 const double H = -0.5 * tot;
                 const int kread = (s + a.M) / a.M - 1;
-                if (a.trace) a.trace[(int64_t)kread * a.R + r] = H;
+                if (a.trace) a.trace[(int64_t)kread * a.R * a.I + out_id] = H;
                 int improved = 0;
                 if (H < best) {
                     best = H;
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             }
             __syncthreads();
             if (*flag && a.best_colour) {
-                int8_t* bc = a.best_colour + (int64_t)r * n;
+                int8_t* bc = a.best_colour + (int64_t)r * a.n_total + off;
 #pragma unroll
                 for (int k = 0; k < MS; ++k) {
                     const int slice = wave + k * W;
@@ -273,8 +279,8 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         }
     }
     if (threadIdx.x == 0) {
-        if (a.best_h) a.best_h[r] = best_at >= 0 ? best : __builtin_inf();
-        if (a.best_step) a.best_step[r] = best_at;
+        if (a.best_h) a.best_h[out_id] = best_at >= 0 ? best : __builtin_inf();
+        if (a.best_step) a.best_step[out_id] = best_at;
     }
 }
 
@@ -339,17 +345,17 @@ int env_int(const char* name, int dflt) {
 }  // namespace
 
 bool persistent_sparse_fits(const Problem* p) {
-    if (p->dense || p->sell_slices == 0) return false;
-    if (lds_bytes(p->sell_slices * 64, 1024) > kLdsLimit) return false;
+    if (p->dense || p->max_slices == 0) return false;
+    if (lds_bytes(p->max_slices * 64, 1024) > kLdsLimit) return false;
     if ((uint64_t)p->sell_entries * 8 > kMaxSellBytes) return false;
-    return pick_variant(p->sell_slices, 0) != nullptr;
+    return pick_variant(p->max_slices, 0) != nullptr;
 }
 
 int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,
                              const float* Ks, const float* sigma, const uint64_t* seeds,
                              int64_t step0, float* theta, uint32_t* phase,
                              const oim_readout* ro, hipStream_t stream) {
-    const int S = p->sell_slices;
+    const int S = p->max_slices;
     const Variant* v = pick_variant(S, env_int("OIM_PERSIST_TB", 0));
     if (!v) v = pick_variant(S, 0);
     if (!v || !persistent_sparse_fits(p))
@@ -358,9 +364,11 @@ int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const flo
     a.sell = reinterpret_cast<const int4*>(p->d_sell);
     a.desc = p->d_sell_desc;
     a.sell_bytes = (uint32_t)(p->sell_entries * 8);
-    a.S = S;
-    a.plane = S * 64;
-    a.n = p->n;
+    a.inst = p->d_inst;
+    a.order = p->d_order;
+    a.I = p->n_inst;
+    a.n_total = p->n;
+    const int plane = S * 64;
     a.q = cfg->q;
     a.steps = cfg->steps;
     a.M = cfg->readout_every;
@@ -379,11 +387,13 @@ int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const flo
     a.R = cfg->R;
     const int qi = cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0;
     KernelFn fn = v->fn[qi];
-    const size_t lds = lds_bytes(a.plane, v->tb);
+    const size_t lds = lds_bytes(plane, v->tb);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
-    hipLaunchKernelGGL(fn, dim3(cfg->R), dim3(v->tb), lds, stream, a);
+    if ((int64_t)cfg->R * p->n_inst > 0x7fffffff)
+        return set_error(OIM_E_ARG, "R * instances too large");
+    hipLaunchKernelGGL(fn, dim3(cfg->R * p->n_inst), dim3(v->tb), lds, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "persistent_sparse_kernel launch");
     return OIM_OK;

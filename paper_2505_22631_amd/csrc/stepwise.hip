@@ -65,7 +65,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const float ns = a.sigma[s] * sqrt_dt * kTurnScale;
     const uint64_t seed = r < a.R ? a.seeds[r] : 0ull;
     float z[4];
-    normals4((uint32_t)m, t, (uint32_t)seed, (uint32_t)(seed >> 32), z);
+    normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int i = 4 * m + j;

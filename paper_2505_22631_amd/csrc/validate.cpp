@@ -119,49 +119,83 @@ int validate_cfg(const Problem* p, const oim_run_cfg* cfg) {
     return OIM_OK;
 }
 
-void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
-                SellImage& out) {
-    const int32_t quads = (n + 3) / 4;
-    const int32_t S = (quads + kSliceQuads - 1) / kSliceQuads;
-    out.slices = S;
-    out.desc.assign((size_t)S, int2{0, 0});
-    int64_t rows4 = 0;  // running offset in int4 rows (64 int4 per row)
-    for (int32_t s = 0; s < S; ++s) {
-        int32_t mx = 0;
-        for (int64_t i = 4LL * s * kSliceQuads; i < std::min<int64_t>(n, 4LL * (s + 1) * kSliceQuads); ++i)
-            mx = std::max<int32_t>(mx, (int32_t)(row_ptr[i + 1] - row_ptr[i]));
-        const int32_t deg = (mx + 3) & ~3;
-        out.desc[s] = int2{(int32_t)rows4, deg};
-        rows4 += 4LL * deg / 2;
+int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t n_inst,
+                    const int32_t* inst_off) {
+    if (n_inst < 1 || n_inst > n) return set_error(OIM_E_ARG, "n_inst must be in [1, n]");
+    if (n_inst == 1 && !inst_off) return OIM_OK;
+    if (!inst_off) return set_error(OIM_E_ARG, "inst_off is NULL");
+    if (inst_off[0] != 0 || inst_off[n_inst] != n)
+        return set_error(OIM_E_ARG, "inst_off must start at 0 and end at n");
+    for (int32_t b = 0; b < n_inst; ++b) {
+        if (inst_off[b + 1] <= inst_off[b])
+            return set_error(OIM_E_ARG, "inst_off must be strictly increasing");
+        for (int32_t i = inst_off[b]; i < inst_off[b + 1]; ++i)
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                if (col_idx[e] < inst_off[b] || col_idx[e] >= inst_off[b + 1])
+                    return set_error(OIM_E_CSR, "entry couples two instances in row " +
+                                                    std::to_string(i));
     }
-    // LDS position of oscillator i: plane (i % 4) of length S*64, slot i / 4.
-    const int64_t plane = (int64_t)S * kSliceQuads;
-    auto lds_off = [plane](int64_t i) { return (int32_t)(8 * ((i & 3) * plane + (i >> 2))); };
-    out.entries.assign((size_t)rows4 * kSliceQuads * 2, int2{0, 0});
-    for (int32_t s = 0; s < S; ++s) {
-        const int32_t base = out.desc[s].x, deg = out.desc[s].y;
-        for (int j = 0; j < 4; ++j) {
-            for (int l = 0; l < kSliceQuads; ++l) {
-                const int64_t i = 4LL * (s * kSliceQuads + l) + j;
-                const int32_t self = (int32_t)std::min<int64_t>(i, n - 1);
-                const int64_t rb = i < n ? row_ptr[i] : 0;
-                const int64_t rl = i < n ? row_ptr[i + 1] - row_ptr[i] : 0;
-                for (int32_t e = 0; e < deg; ++e) {
-                    int2 v;
-                    if (e < rl) {
-                        v.x = lds_off(col_idx[rb + e]);
-                        float w = J[rb + e];
-                        std::memcpy(&v.y, &w, 4);
-                    } else {
-                        v.x = lds_off(self);
-                        v.y = 0;
+    return OIM_OK;
+}
+
+void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+                int32_t n_inst, const int32_t* inst_off, SellImage& out) {
+    out.desc.clear();
+    out.entries.clear();
+    out.inst.clear();
+    out.max_slices = 0;
+    int64_t rows4 = 0;  // running offset in int4 rows (64 int4 per row)
+    int32_t slice_base = 0;
+    for (int32_t b = 0; b < n_inst; ++b) {
+        const int32_t o = inst_off ? inst_off[b] : 0;
+        const int32_t nb = inst_off ? inst_off[b + 1] - inst_off[b] : n;
+        const int32_t quads = (nb + 3) / 4;
+        const int32_t S = (quads + kSliceQuads - 1) / kSliceQuads;
+        out.inst.push_back(int4{slice_base, S, o, nb});
+        out.max_slices = std::max(out.max_slices, S);
+        // LDS position of local oscillator i: plane (i % 4) of length S*64, slot i / 4.
+        const int64_t plane = (int64_t)S * kSliceQuads;
+        auto lds_off = [plane](int64_t i) { return (int32_t)(8 * ((i & 3) * plane + (i >> 2))); };
+        for (int32_t s = 0; s < S; ++s) {
+            int32_t mx = 0;
+            const int64_t lo = 4LL * s * kSliceQuads, hi = std::min<int64_t>(nb, 4LL * (s + 1) * kSliceQuads);
+            for (int64_t i = lo; i < hi; ++i)
+                mx = std::max<int32_t>(mx, (int32_t)(row_ptr[o + i + 1] - row_ptr[o + i]));
+            const int32_t deg = (mx + 3) & ~3;
+            out.desc.push_back(int2{(int32_t)rows4, deg});
+            const size_t first = out.entries.size();
+            out.entries.resize(first + (size_t)4 * deg / 2 * kSliceQuads * 2, int2{0, 0});
+            for (int j = 0; j < 4; ++j) {
+                for (int l = 0; l < kSliceQuads; ++l) {
+                    const int64_t i = 4LL * (s * kSliceQuads + l) + j;  // local index
+                    const int32_t self = (int32_t)std::min<int64_t>(i, nb - 1);
+                    const int64_t rb = i < nb ? row_ptr[o + i] : 0;
+                    const int64_t rl = i < nb ? row_ptr[o + i + 1] - row_ptr[o + i] : 0;
+                    for (int32_t e = 0; e < deg; ++e) {
+                        int2 v;
+                        if (e < rl) {
+                            v.x = lds_off(col_idx[rb + e] - o);
+                            float w = J[rb + e];
+                            std::memcpy(&v.y, &w, 4);
+                        } else {
+                            v.x = lds_off(self);
+                            v.y = 0;
+                        }
+                        const int64_t q4 = ((int64_t)j * (deg / 2) + e / 2) * kSliceQuads + l;
+                        out.entries[first + (size_t)(q4 * 2 + (e & 1))] = v;
                     }
-                    const int64_t q4 = ((int64_t)base + j * (deg / 2) + e / 2) * kSliceQuads + l;
-                    out.entries[(size_t)(q4 * 2 + (e & 1))] = v;
                 }
             }
+            rows4 += 4LL * deg / 2;
         }
+        slice_base += S;
     }
+    out.slices = slice_base;
+    out.order.resize(n_inst);
+    for (int32_t b = 0; b < n_inst; ++b) out.order[b] = b;
+    std::stable_sort(out.order.begin(), out.order.end(), [&](int32_t x, int32_t y) {
+        return out.inst[x].y > out.inst[y].y || (out.inst[x].y == out.inst[y].y && out.inst[x].w > out.inst[y].w);
+    });
 }
 
 }  // namespace oim

@@ -124,3 +124,30 @@ def test_valid_problem_without_gpu_reports_hip_error(oim):
     g = synth.cycle(8)
     st, msg = _csr_call(oim, 8, g.row_ptr, g.col, -g.w)
     assert st == 7 and msg
+
+
+def test_block_batch_validation(oim):
+    L = oim.lib()
+    a = synth.cycle(6)
+    b = synth.cycle(4)
+    # a proper block-diagonal batch passes validation (then fails on the missing GPU)
+    rows = np.concatenate([a.row_ptr, a.row_ptr[-1] + b.row_ptr[1:]])
+    cols = np.concatenate([a.col, b.col + 6]).astype(np.int32)
+    J = -np.ones(cols.size, np.float32)
+    off = np.array([0, 6, 10], np.int32)
+
+    def call(offs, c=cols):
+        h = ctypes.c_void_p()
+        o = np.ascontiguousarray(offs, np.int32)
+        c = np.ascontiguousarray(c, np.int32)
+        rp = np.ascontiguousarray(rows, np.int64)
+        return L.oim_problem_from_csr_blocks(10, c.size, rp.ctypes.data_as(ctypes.c_void_p),
+                                             c.ctypes.data_as(ctypes.c_void_p),
+                                             J.ctypes.data_as(ctypes.c_void_p), len(o) - 1,
+                                             o.ctypes.data_as(ctypes.c_void_p), 0, ctypes.byref(h))
+    import torch
+    if not torch.cuda.is_available():
+        assert call(off) == 7
+    assert call([0, 5, 10]) == 2           # an edge crosses the boundary
+    assert call([0, 6, 6, 10]) == 1        # empty instance
+    assert call([1, 6, 10]) == 1           # does not start at 0

@@ -317,3 +317,60 @@ def test_stepwise_readout_and_resume(dev, oim, orc):
     # and the persistent kernel reaches the same phases within the parity bound
     th_p, _ = _gpu_run(oim, prob, th0, K, Ks, sg, synth.seeds(3, 2), 2)
     assert wrapdiff(th_p, th).max() < TOL_RAD
+
+
+# ------------------------------------------------------ block-diagonal batch ----
+def _batch(count, seed):
+    pairs = synth.planted_batch(count, 100, 600, 4.6, 3, seed)
+    graphs = [g for g, _ in pairs]
+    off = np.cumsum([0] + [g.n for g in graphs]).astype(np.int32)
+    ei, ej = [], []
+    for g, o in zip(graphs, off[:-1]):
+        a, b, _ = g.upper_edges()
+        ei.append(a + o)
+        ej.append(b + o)
+    big = synth.csr_from_edges(int(off[-1]), np.concatenate(ei), np.concatenate(ej),
+                               np.ones(sum(len(x) for x in ei)))
+    return big, off, graphs
+
+
+def test_ragged_batch_parity_and_readout(dev, oim, orc):
+    big, off, graphs = _batch(24, seed=2)
+    J = -np.ones(big.nnz, np.float32)
+    prob = oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, J, off)
+    assert prob.info["n_instances"] == 24
+    K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 3, 5000, 100)
+    R = 2
+    th0 = synth.theta0(R, big.n, seed=12)
+    sd = synth.seeds(R, 40)
+    w0 = _phase_words(th0)
+    got, ro, w = _gpu_run(oim, prob, th0, K, Ks, sg, sd, 3, step0=3, readout_every=25,
+                          want_best=True, phase=w0)
+    want = orc.run_csr_blocks(big.row_ptr, big.col, J, off, th0, q=3, dt=DT, K=K, Ks=Ks,
+                              sigma=sg, seeds=sd, step0=3)
+    err = wrapdiff(got, want).max()
+    print(f"batch of 24, n_total={big.n}: max |dtheta| = {err:.3e} rad", flush=True)
+    assert err < TOL_RAD
+    tr = ro["trace"]
+    assert tr.shape == (4, R * 24)
+    for r in range(R):
+        for b, g in enumerate(graphs):
+            cols = _colours_from_words(w[r, off[b]:off[b + 1]], 3)
+            Jb = -np.ones(g.nnz)
+            # the last readout is this instance's Eq. 2 energy = conflicts for J = -1
+            assert tr[-1, r * 24 + b] == orc.h_model(g.row_ptr, g.col, Jb, 3, cols)
+            bc = ro["best_colour"][r, off[b]:off[b + 1]]
+            assert ro["best_h"][r * 24 + b] == orc.conflicts(g.row_ptr, g.col, Jb, bc)
+
+
+def test_batch_instance_zero_matches_standalone(dev, oim, orc):
+    big, off, graphs = _batch(5, seed=7)
+    g0 = graphs[0]
+    K, Ks, sg = ramp_schedule(10.0, 3, 1000, 60)
+    th0 = synth.theta0(3, big.n, seed=2)
+    sd = synth.seeds(3, 1)
+    with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, -np.ones(big.nnz), off) as pb, \
+            oim.Problem.from_csr(g0.n, g0.row_ptr, g0.col, -np.ones(g0.nnz)) as p0:
+        a, _ = _gpu_run(oim, pb, th0, K, Ks, sg, sd, 3)
+        b, _ = _gpu_run(oim, p0, np.ascontiguousarray(th0[:, :g0.n]), K, Ks, sg, sd, 3)
+    np.testing.assert_array_equal(a[:, :g0.n], b)

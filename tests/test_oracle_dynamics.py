@@ -165,3 +165,73 @@ def test_resume_and_replica_independence(orc):
     one = orc.run_csr(g.row_ptr, g.col, -g.w, th0[1:2], q=2, dt=0.01, K=K, Ks=Ks, sigma=sig,
                       seeds=sd[1:2])
     np.testing.assert_array_equal(full[1:2], one)
+
+
+def _concat(graphs):
+    """Block-diagonal CSR of several graphs and the instance offsets."""
+    off = np.cumsum([0] + [g.n for g in graphs]).astype(np.int32)
+    ei, ej, w = [], [], []
+    for g, o in zip(graphs, off[:-1]):
+        a, b, c = g.upper_edges()
+        ei.append(a + o)
+        ej.append(b + o)
+        w.append(c)
+    return synth.csr_from_edges(int(off[-1]), np.concatenate(ei), np.concatenate(ej),
+                                np.concatenate(w)), off
+
+
+def test_block_batch_instances(orc):
+    # instance 0 of a block-diagonal batch is the standalone run of its graph;
+    # every instance draws its noise with local indices and its instance number
+    gs = [synth.random_small(n, 0.3, seed=n, weights="pm1") for n in (9, 14, 6)]
+    big, off = _concat(gs)
+    steps = 25
+    kw = dict(q=2, dt=0.01, K=synth.ramp(0.1, 1.0, steps), Ks=synth.ramp(0, 2.0, steps),
+              sigma=synth.const(0.1, steps), seeds=synth.seeds(2, 5), step0=4)
+    th0 = synth.theta0(2, big.n, seed=1)
+    out = orc.run_csr_blocks(big.row_ptr, big.col, -big.w, off, th0, **kw)
+    alone = orc.run_csr(gs[0].row_ptr, gs[0].col, -gs[0].w, th0[:, :9], **kw)
+    np.testing.assert_array_equal(out[:, :9], alone)
+    # noise-only check of instance 2 (K = Ks = 0)
+    kw0 = dict(kw, K=np.zeros(steps), Ks=np.zeros(steps))
+    out0 = orc.run_csr_blocks(big.row_ptr, big.col, -big.w, off, th0, **kw0)
+    acc = th0[1, off[2]:off[3]].astype(np.float64).copy()
+    for s in range(steps):
+        acc += float(kw["sigma"][s]) * np.sqrt(0.01) * np.array([orc.normal(int(kw["seeds"][1]), i, 4 + s, 2)
+                                               for i in range(6)])
+    assert np.max(_wrapdiff(out0[1, off[2]:off[3]], np.mod(acc, TWO_PI))) < 1e-12
+    # and a different instance number gives a different stream
+    assert orc.normal(5, 3, 7, 1) != orc.normal(5, 3, 7, 0)
+
+
+@pytest.mark.parametrize("q", [2, 3])
+def test_adjoint_matches_finite_differences(orc, q):
+    # The FP64 adjoint's gradient of the relaxed cut against central
+    # differences of the same loss, per schedule entry.
+    g = synth.random_small(12, 0.4, seed=21, weights="pm1")
+    J = -g.w.astype(np.float64)
+    steps, dt = 30, 0.02
+    K = synth.ramp(0.2, 1.5, steps).astype(np.float64)
+    Ks = synth.ramp(0.0, 2.0, steps).astype(np.float64)
+    sg = synth.const(0.15, steps).astype(np.float64)
+    th0 = synth.theta0(2, 12, seed=9).astype(np.float64)
+    sd = synth.seeds(2, 3)
+
+    def loss(K_, Ks_, sg_):
+        th = orc.run_csr(g.row_ptr, g.col, J, th0, q=q, dt=dt, K=K_, Ks=Ks_, sigma=sg_,
+                         seeds=sd, step0=5)
+        return orc.relaxed_cut(g.row_ptr, g.col, J, th)
+
+    L, gK, gKs, gS = orc.adjoint_csr(g.row_ptr, g.col, J, th0, q=q, dt=dt, K=K, Ks=Ks, sigma=sg,
+                                     seeds=sd, step0=5)
+    assert L == pytest.approx(loss(K, Ks, sg), rel=1e-12)
+    eps = 1e-5
+    for s in (0, 7, 18, 29):
+        for vec, grad in ((K, gK), (Ks, gKs), (sg, gS)):
+            up, dn = vec.copy(), vec.copy()
+            up[s] += eps
+            dn[s] -= eps
+            args_up = [up if v is vec else v for v in (K, Ks, sg)]
+            args_dn = [dn if v is vec else v for v in (K, Ks, sg)]
+            fd = (loss(*args_up) - loss(*args_dn)) / (2 * eps)
+            assert grad[s] == pytest.approx(fd, rel=1e-5, abs=1e-9)
