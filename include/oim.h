@@ -213,6 +213,56 @@ int oim_conflicts(oim_problem p, int32_t R, const int8_t* colour, int64_t* confl
 int oim_energy(oim_problem p, int32_t q, int32_t R, const float* theta, const int8_t* colour,
                double* h_model, double* h_eq6, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Schedule gradients: adjoint of the fixed-noise trajectory (the annealing
+ * schedules K(t), Ks(t) and the noise amplitude of Sec. II-D / Eq. 5 as
+ * tunable parameters; sparse problems, every instance of at most 4096
+ * oscillators).
+ *
+ * Loss, per replica r and instance b, at the phases after the last step:
+ *     L_rb = sum_{i<j in b} w_ij (1 - cos(theta_i - theta_j)) / 2,  w = -J
+ * (the relaxed cut: the cut value when every phase sits at 0 or pi).  The
+ * gradients are those of L = sum_rb L_rb with respect to K[s], Ks[s] and
+ * sigma[s] of the trajectory oim_run integrates with the same arguments
+ * (same noise stream; the wrap of the phase has derivative 1).
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t q;                /* SHIL order, 2..16 */
+    int32_t R;                /* replicas per instance */
+    int32_t steps;            /* Euler-Maruyama steps, >= 0 */
+    float dt;                 /* step, > 0 */
+    int32_t checkpoint_every; /* C >= 1: phase words kept every C steps */
+    uint32_t flags;           /* must be 0 */
+} oim_adjoint_cfg;
+
+/* Size of the checkpoint buffer in uint32 words:
+ * ceil(steps / C) * R * (instance slots of the problem). */
+int oim_adjoint_checkpoint_words(oim_problem p, const oim_adjoint_cfg* cfg, int64_t* words);
+
+/* Forward pass.  theta0: device FP32 [R][n] initial phases (radians);
+ * ckpt: device uint32 [words], caller-owned, written with the phase words of
+ * steps 0, C, 2C, ...; theta_T: NULL or device FP32 [R][n], the final
+ * phases; loss: NULL or device FP64 [R * I], entry r * I + b.  The other
+ * arguments are those of oim_run (schedules [steps], seeds [R], step0).
+ * Errors: OIM_E_ARG, OIM_E_UNSUPPORTED (dense problem or an instance above
+ * 4096 oscillators), OIM_E_HIP. */
+int oim_adjoint_forward(oim_problem p, const oim_adjoint_cfg* cfg, const float* K,
+                        const float* Ks, const float* sigma, const uint64_t* seeds,
+                        int64_t step0, const float* theta0, uint32_t* ckpt, float* theta_T,
+                        double* loss, hipStream_t stream);
+
+/* Backward pass from the checkpoints of a forward pass with the same
+ * arguments: recomputes every C-step segment from its checkpoint, runs the
+ * adjoint recurrence back through it, and writes dL/dK, dL/dKs, dL/dsigma as
+ * device FP64 [steps] (sums over replicas and instances in a fixed order).
+ * Uses a workspace cached in p (C * R * slots words plus 128 bytes per step
+ * and workgroup); one stream at a time per problem.  Errors as the forward
+ * pass, plus OIM_E_NOMEM. */
+int oim_adjoint_backward(oim_problem p, const oim_adjoint_cfg* cfg, const float* K,
+                         const float* Ks, const float* sigma, const uint64_t* seeds,
+                         int64_t step0, const uint32_t* ckpt, double* gK, double* gKs,
+                         double* gsigma, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -49,6 +49,9 @@ def lib():
         L.orc_adjoint_csr.argtypes = [_i32, _P, _P, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P,
                                       _P, _P, _P, _P, _P, _P]
         L.orc_adjoint_csr.restype = ctypes.c_int
+        L.orc_adjoint_csr_blocks.argtypes = [_i32, _P, _P, _P, _i32, _P, _i32, _i32, _i32, _i64,
+                                             _f64, _P, _P, _P, _P, _P, _P, _P, _P, _P]
+        L.orc_adjoint_csr_blocks.restype = ctypes.c_int
         L.orc_run_dense.argtypes = [_i32, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P, _P,
                                     _i32]
         L.orc_run_dense.restype = ctypes.c_int
@@ -149,9 +152,11 @@ def run_csr_blocks(row_ptr, col, J, inst_off, theta0, *, q, dt, K, Ks, sigma, se
     return th
 
 
-def adjoint_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0):
-    """Relaxed-cut loss of the final phases (sum over replicas) and its gradient with
-    respect to the per-step K, Ks and sigma of the fixed-noise trajectory."""
+def adjoint_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0,
+                inst_off=None):
+    """Relaxed-cut loss of the final phases (sum over replicas and instances) and its
+    gradient with respect to the per-step K, Ks and sigma of the fixed-noise
+    trajectory.  inst_off splits the graph into block-diagonal instances."""
     rp = _c(row_ptr, np.int64)
     cl = _c(col, np.int32)
     Jv = _c(J, np.float64)
@@ -159,14 +164,17 @@ def adjoint_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0)
     R, n = th.shape
     steps = len(K)
     sd = _c(seeds, np.uint64)
+    io = _c([0, n] if inst_off is None else inst_off, np.int32)
+    assert sd.shape == (R,) and rp.shape == (n + 1,) and io[-1] == n
     loss = np.zeros(1)
     gK, gKs, gS = np.zeros(steps), np.zeros(steps), np.zeros(steps)
-    rc = lib().orc_adjoint_csr(n, _ptr(rp), _ptr(cl), _ptr(Jv), int(q), R, steps, int(step0),
-                               float(dt), _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
-                               _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), _ptr(loss),
-                               _ptr(gK), _ptr(gKs), _ptr(gS))
+    rc = lib().orc_adjoint_csr_blocks(n, _ptr(rp), _ptr(cl), _ptr(Jv), len(io) - 1, _ptr(io),
+                                      int(q), R, steps, int(step0), float(dt),
+                                      _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
+                                      _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), _ptr(loss),
+                                      _ptr(gK), _ptr(gKs), _ptr(gS))
     if rc != 0:
-        raise ValueError("orc_adjoint_csr rejected its arguments")
+        raise ValueError("orc_adjoint_csr_blocks rejected its arguments")
     return float(loss[0]), gK, gKs, gS
 
 

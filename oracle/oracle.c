@@ -294,17 +294,34 @@ int orc_abi_version(void) { return 1; }
 /* The wrap into one period has derivative 1 almost everywhere.  All sums    */
 /* run over replicas too (one schedule drives every replica).                */
 /* ------------------------------------------------------------------------ */
-int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
-                    int32_t q, int32_t R, int32_t steps, int64_t step0, double dt,
-                    const double* K, const double* Ks, const double* sigma,
-                    const uint64_t* seeds, const double* theta0, double* loss, double* gK,
-                    double* gKs, double* gS) {
-    if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0)) return -1;
+/* A block-diagonal batch (instances [inst_off[b], inst_off[b+1])) draws its */
+/* noise per instance, as the forward integrator does; the loss and the      */
+/* gradients are sums over instances and replicas.                           */
+int orc_adjoint_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col,
+                           const double* J, int32_t n_inst, const int32_t* inst_off, int32_t q,
+                           int32_t R, int32_t steps, int64_t step0, double dt, const double* K,
+                           const double* Ks, const double* sigma, const uint64_t* seeds,
+                           const double* theta0, double* loss, double* gK, double* gKs,
+                           double* gS) {
+    if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0) || n_inst < 1) return -1;
     const size_t N = (size_t)n;
+    uint32_t* inst_of = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    uint32_t* local = (uint32_t*)malloc(sizeof(uint32_t) * N);
+    if (!inst_of || !local) { free(inst_of); free(local); return -1; }
+    for (int32_t i = 0; i < n; ++i) { inst_of[i] = 0; local[i] = (uint32_t)i; }
+    if (inst_off && n_inst > 1)
+        for (int32_t b = 0; b < n_inst; ++b)
+            for (int32_t i = inst_off[b]; i < inst_off[b + 1]; ++i) {
+                inst_of[i] = (uint32_t)b;
+                local[i] = (uint32_t)(i - inst_off[b]);
+            }
     double* traj = (double*)malloc(sizeof(double) * N * (size_t)(steps + 1));
     double* lam = (double*)malloc(sizeof(double) * N);
     double* nxt = (double*)malloc(sizeof(double) * N);
-    if (!traj || !lam || !nxt) { free(traj); free(lam); free(nxt); return -1; }
+    if (!traj || !lam || !nxt) {
+        free(traj); free(lam); free(nxt); free(inst_of); free(local);
+        return -1;
+    }
     for (int32_t s = 0; s < steps; ++s) gK[s] = gKs[s] = gS[s] = 0.0;
     double total = 0.0;
     const double sq = sqrt(dt);
@@ -312,11 +329,11 @@ int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const
         /* forward, keeping every state */
         memcpy(traj, theta0 + (size_t)r * N, sizeof(double) * N);
         if (run_common(n, row_ptr, col, J, NULL, q, 1, 0, step0, dt, K, Ks, sigma, seeds + r,
-                       traj, 1, 1, NULL) != 0) { total = NAN; break; }
+                       traj, 1, n_inst, inst_off) != 0) { total = NAN; break; }
         for (int32_t s = 0; s < steps; ++s) {
             memcpy(traj + N * (s + 1), traj + N * s, sizeof(double) * N);
             if (run_common(n, row_ptr, col, J, NULL, q, 1, 1, step0 + s, dt, K + s, Ks + s,
-                           sigma + s, seeds + r, traj + N * (s + 1), 1, 1, NULL) != 0) {
+                           sigma + s, seeds + r, traj + N * (s + 1), 1, n_inst, inst_off) != 0) {
                 total = NAN;
                 break;
             }
@@ -345,7 +362,7 @@ int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const
                 nxt[k] = lam[k] + dt * (K[s] * cc - (double)q * Ks[s] * cos((double)q * th[k]) * lam[k]);
                 gK[s] += -dt * lam[k] * csin;
                 gKs[s] += -dt * lam[k] * sin((double)q * th[k]);
-                gS[s] += sq * lam[k] * orc_normal(seeds[r], (uint32_t)k, t);
+                gS[s] += sq * lam[k] * orc_normal_b(seeds[r], local[k], t, inst_of[k]);
             }
             memcpy(lam, nxt, sizeof(double) * N);
         }
@@ -354,5 +371,16 @@ int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const
     free(traj);
     free(lam);
     free(nxt);
+    free(inst_of);
+    free(local);
     return 0;
+}
+
+int orc_adjoint_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                    int32_t q, int32_t R, int32_t steps, int64_t step0, double dt,
+                    const double* K, const double* Ks, const double* sigma,
+                    const uint64_t* seeds, const double* theta0, double* loss, double* gK,
+                    double* gKs, double* gS) {
+    return orc_adjoint_csr_blocks(n, row_ptr, col, J, 1, NULL, q, R, steps, step0, dt, K, Ks,
+                                  sigma, seeds, theta0, loss, gK, gKs, gS);
 }

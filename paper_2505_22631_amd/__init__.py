@@ -6,7 +6,9 @@ supplies device memory and the current HIP stream.
 
 Functions carry the C names: oim_problem_from_csr, oim_problem_from_dense,
 oim_problem_destroy, oim_problem_info_get, oim_run, oim_round, oim_cut,
-oim_conflicts, oim_energy.  `Problem` and `run` are small conveniences on top.
+oim_conflicts, oim_energy, oim_adjoint_forward, oim_adjoint_backward.
+`Problem` and `run` are small conveniences on top; `autograd.RelaxedCut` puts
+the adjoint kernels behind a torch.autograd.Function.
 """
 from __future__ import annotations
 
@@ -18,14 +20,15 @@ import torch
 
 from . import _lib
 from ._lib import (OIM_LOOP_AUTO, OIM_LOOP_PERSISTENT, OIM_LOOP_STEPWISE, OIM_PREC_BF16X3,
-                   OIM_PREC_FP32, OimError, Readout, RunCfg, check, lib)
+                   OIM_PREC_FP32, AdjointCfg, OimError, Readout, RunCfg, check, lib)
 
 __all__ = [
     "OIM_LOOP_AUTO", "OIM_LOOP_PERSISTENT", "OIM_LOOP_STEPWISE", "OIM_PREC_FP32",
     "OIM_PREC_BF16X3", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
     "oim_problem_from_csr_blocks", "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
     "oim_round", "oim_cut", "oim_conflicts", "oim_energy", "oim_phase_from_theta",
-    "oim_theta_from_phase", "run", "n_readouts",
+    "oim_theta_from_phase", "oim_adjoint_checkpoint_words", "oim_adjoint_forward",
+    "oim_adjoint_backward", "run", "n_readouts",
 ]
 
 
@@ -144,6 +147,54 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
                         _dev(theta, torch.float32, None, "theta"),
                         _dev(phase, torch.uint32, (R, n), "phase", True), ctypes.byref(ro),
                         _stream(stream)))
+
+
+def _adj_cfg(q, R, steps, dt, checkpoint_every):
+    return AdjointCfg(int(q), int(R), int(steps), float(dt), int(checkpoint_every), 0)
+
+
+def oim_adjoint_checkpoint_words(h, *, q, R, steps, dt, checkpoint_every) -> int:
+    cfg = _adj_cfg(q, R, steps, dt, checkpoint_every)
+    w = ctypes.c_int64(0)
+    check(lib().oim_adjoint_checkpoint_words(h, ctypes.byref(cfg), ctypes.byref(w)))
+    return int(w.value)
+
+
+def oim_adjoint_forward(h, n, theta0, K, Ks, sigma, seeds, ckpt, *, q, dt, checkpoint_every,
+                        step0=0, theta_T=None, loss=None, stream=None):
+    """Forward pass of the schedule adjoint from theta0[R][n]: checkpoints
+    into ckpt (uint32 [words]), optional final phases and per-(replica,
+    instance) relaxed cut (FP64 [R * I])."""
+    if theta0.dim() != 2 or theta0.shape[1] != n:
+        raise ValueError("theta0 must be [R][n]")
+    R, steps = int(theta0.shape[0]), int(K.shape[0])
+    cfg = _adj_cfg(q, R, steps, dt, checkpoint_every)
+    RI = R * int(oim_problem_info_get(h)["n_instances"])
+    check(lib().oim_adjoint_forward(h, ctypes.byref(cfg), _dev(K, torch.float32, (steps,), "K"),
+                                    _dev(Ks, torch.float32, (steps,), "Ks"),
+                                    _dev(sigma, torch.float32, (steps,), "sigma"),
+                                    _dev(seeds, torch.uint64, (R,), "seeds"), int(step0),
+                                    _dev(theta0, torch.float32, None, "theta0"),
+                                    _dev(ckpt, torch.uint32, None, "ckpt", steps == 0),
+                                    _dev(theta_T, torch.float32, (R, n), "theta_T", True),
+                                    _dev(loss, torch.float64, (RI,), "loss", True),
+                                    _stream(stream)))
+
+
+def oim_adjoint_backward(h, R, K, Ks, sigma, seeds, ckpt, gK, gKs, gsigma, *, q, dt,
+                         checkpoint_every, step0=0, stream=None):
+    """Backward pass: dL/dK, dL/dKs, dL/dsigma (FP64 [steps]) from the checkpoints."""
+    steps = int(K.shape[0])
+    cfg = _adj_cfg(q, R, steps, dt, checkpoint_every)
+    check(lib().oim_adjoint_backward(h, ctypes.byref(cfg), _dev(K, torch.float32, (steps,), "K"),
+                                     _dev(Ks, torch.float32, (steps,), "Ks"),
+                                     _dev(sigma, torch.float32, (steps,), "sigma"),
+                                     _dev(seeds, torch.uint64, (R,), "seeds"), int(step0),
+                                     _dev(ckpt, torch.uint32, None, "ckpt", steps == 0),
+                                     _dev(gK, torch.float64, (steps,), "gK"),
+                                     _dev(gKs, torch.float64, (steps,), "gKs"),
+                                     _dev(gsigma, torch.float64, (steps,), "gsigma"),
+                                     _stream(stream)))
 
 
 def oim_phase_from_theta(theta, phase=None, stream=None):

@@ -27,6 +27,11 @@ class Readout(ctypes.Structure):
     _fields_ = [("trace", _P), ("best_h", _P), ("best_step", _P), ("best_colour", _P)]
 
 
+class AdjointCfg(ctypes.Structure):
+    _fields_ = [("q", _i32), ("R", _i32), ("steps", _i32), ("dt", _f32),
+                ("checkpoint_every", _i32), ("flags", _u32)]
+
+
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", _i32), ("is_dense", _i32), ("nnz", _i64), ("integer_weights", _i32),
                 ("n_instances", _i32), ("max_abs_row_sum", ctypes.c_double),
@@ -52,6 +57,12 @@ PROTOTYPES = {
     "oim_cut": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P]),
     "oim_conflicts": (ctypes.c_int, [_P, _i32, _P, _P, _P]),
     "oim_energy": (ctypes.c_int, [_P, _i32, _i32, _P, _P, _P, _P, _P]),
+    "oim_adjoint_checkpoint_words": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg),
+                                                    ctypes.POINTER(_i64)]),
+    "oim_adjoint_forward": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg), _P, _P, _P, _P, _i64,
+                                           _P, _P, _P, _P, _P]),
+    "oim_adjoint_backward": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg), _P, _P, _P, _P,
+                                            _i64, _P, _P, _P, _P, _P]),
 }
 
 _lib = None

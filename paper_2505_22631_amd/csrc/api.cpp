@@ -1,6 +1,8 @@
 // api.cpp -- the extern "C" entry points of include/oim.h.
 // Host-side validation always runs before the first HIP call of an entry
 // point; device memory of a problem is owned by its oim_problem handle.
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -41,6 +43,7 @@ void release(Problem* p) {
     hipFree(p->d_inst);
     hipFree(p->d_order);
     hipFree(p->d_work);
+    hipFree(p->d_adj);
     dense_release(p);
     p->magic = kDeadMagic;
     delete p;
@@ -118,6 +121,12 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     p->n = n;
     p->nnz = nnz;
     p->n_inst = n_inst;
+    p->max_inst_n = n;
+    if (n_inst > 1) {
+        p->max_inst_n = 0;
+        for (int32_t b = 0; b < n_inst; ++b)
+            p->max_inst_n = std::max(p->max_inst_n, inst_off[b + 1] - inst_off[b]);
+    }
     weight_stats(p, n, row_ptr, col_idx, J);
     SellImage img;
     build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img);
@@ -242,6 +251,63 @@ __attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_
         return launch_persistent_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro,
                                         stream);
     return launch_stepwise_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
+}
+
+__attribute__((visibility("default"))) int oim_adjoint_checkpoint_words(oim_problem h,
+                                                                        const oim_adjoint_cfg* cfg,
+                                                                        int64_t* words) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (!words) return set_error(OIM_E_ARG, "words is NULL");
+    const int st = validate_adjoint_cfg(p, cfg);
+    if (st) return st;
+    *words = adjoint_checkpoint_words(p, cfg);
+    return OIM_OK;
+}
+
+namespace {
+int adjoint_common(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
+                   const float* sigma, const uint64_t* seeds, int64_t step0) {
+    int st = validate_adjoint_cfg(p, cfg);
+    if (st) return st;
+    if (!seeds) return set_error(OIM_E_ARG, "seeds is NULL");
+    if (cfg->steps > 0 && (!K || !Ks || !sigma))
+        return set_error(OIM_E_ARG, "schedule pointer is NULL");
+    if (step0 < 0 || step0 + (int64_t)cfg->steps > ((int64_t)1 << 32))
+        return set_error(OIM_E_ARG, "global step index must stay below 2^32");
+    return check_device(p);
+}
+}  // namespace
+
+__attribute__((visibility("default"))) int oim_adjoint_forward(
+    oim_problem h, const oim_adjoint_cfg* cfg, const float* K, const float* Ks, const float* sigma,
+    const uint64_t* seeds, int64_t step0, const float* theta0, uint32_t* ckpt, float* theta_T,
+    double* loss, hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    int st = adjoint_common(p, cfg, K, Ks, sigma, seeds, step0);
+    if (st) return st;
+    if (!theta0) return set_error(OIM_E_ARG, "theta0 is NULL");
+    if (cfg->steps > 0 && !ckpt) return set_error(OIM_E_ARG, "ckpt is NULL");
+    return launch_adjoint_forward(p, cfg, K, Ks, sigma, seeds, step0, theta0, ckpt, theta_T, loss,
+                                  stream);
+}
+
+__attribute__((visibility("default"))) int oim_adjoint_backward(
+    oim_problem h, const oim_adjoint_cfg* cfg, const float* K, const float* Ks, const float* sigma,
+    const uint64_t* seeds, int64_t step0, const uint32_t* ckpt, double* gK, double* gKs,
+    double* gsigma, hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    int st = adjoint_common(p, cfg, K, Ks, sigma, seeds, step0);
+    if (st) return st;
+    if (cfg->steps == 0) return OIM_OK;
+    if (!ckpt || !gK || !gKs || !gsigma) return set_error(OIM_E_ARG, "NULL array");
+    return launch_adjoint_backward(p, cfg, K, Ks, sigma, seeds, step0, ckpt, gK, gKs, gsigma,
+                                   stream);
 }
 
 __attribute__((visibility("default"))) int oim_phase_from_theta(int64_t count,

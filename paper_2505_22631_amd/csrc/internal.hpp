@@ -15,6 +15,7 @@ constexpr uint32_t kProblemMagic = 0x4f494d50u;  // "OIMP"
 constexpr uint32_t kDeadMagic = 0xdeadbeefu;
 constexpr int kMaxQ = 16;
 constexpr int kSliceQuads = 64;  // quads (4 oscillators) per slice = one wave's lanes
+constexpr int kAdjMaxN = 4096;   // largest instance the adjoint kernels hold in LDS
 
 // Sliced-ELL image of a symmetric CSR, laid out for the LDS-resident kernel:
 // slice s covers quads 64s..64s+63 (oscillators 4*quad + j, j = 0..3).  All
@@ -54,6 +55,7 @@ struct Problem {
 
     // instances of a block-diagonal batch (1 for a single graph)
     int32_t n_inst = 1;
+    int32_t max_inst_n = 0;  // largest instance (oscillators)
     int4* d_inst = nullptr;
     int32_t* d_order = nullptr;
     int32_t max_slices = 0;
@@ -72,6 +74,10 @@ struct Problem {
     // cached workspace for the stepwise / dense loops
     void* d_work = nullptr;
     size_t work_bytes = 0;
+
+    // cached scratch of the adjoint backward pass
+    void* d_adj = nullptr;
+    size_t adj_bytes = 0;
 };
 
 // error plumbing (errors.cpp)
@@ -107,6 +113,16 @@ void dense_release(Problem* p);
 int launch_phase_convert(int64_t count, const float* theta_in, uint32_t* phase_out,
                          const uint32_t* phase_in, float* theta_out, hipStream_t s);
 bool persistent_sparse_fits(const Problem* p);
+int validate_adjoint_cfg(const Problem* p, const oim_adjoint_cfg* cfg);
+int64_t adjoint_checkpoint_words(const Problem* p, const oim_adjoint_cfg* cfg);
+int launch_adjoint_forward(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
+                           const float* sigma, const uint64_t* seeds, int64_t step0,
+                           const float* theta0, uint32_t* ckpt, float* thetaT, double* loss,
+                           hipStream_t stream);
+int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
+                            const float* sigma, const uint64_t* seeds, int64_t step0,
+                            const uint32_t* ckpt, double* gK, double* gKs, double* gS,
+                            hipStream_t stream);
 int launch_round(int32_t q, int64_t count, const float* theta, int8_t* colour, hipStream_t s);
 int launch_cut(const Problem* p, int32_t R, const int8_t* colour, int64_t* cut_i64,
                double* cut_f64, hipStream_t s);

@@ -2,6 +2,7 @@
 // Nothing here touches the HIP runtime, so every rejection path can be
 // exercised on a machine without a GPU.
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -116,6 +117,23 @@ int validate_cfg(const Problem* p, const oim_run_cfg* cfg) {
         return set_error(OIM_E_UNSUPPORTED, "BF16X3 applies to dense problems only");
     if ((int64_t)cfg->R * p->n > ((int64_t)1 << 40))
         return set_error(OIM_E_ARG, "R * n too large");
+    return OIM_OK;
+}
+
+int validate_adjoint_cfg(const Problem* p, const oim_adjoint_cfg* cfg) {
+    if (!cfg) return set_error(OIM_E_ARG, "cfg is NULL");
+    if (cfg->q < 2 || cfg->q > kMaxQ) return set_error(OIM_E_ARG, "q must be in [2, 16]");
+    if (cfg->R < 1) return set_error(OIM_E_ARG, "R must be >= 1");
+    if (cfg->steps < 0) return set_error(OIM_E_ARG, "steps must be >= 0");
+    if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt))
+        return set_error(OIM_E_ARG, "dt must be finite and > 0");
+    if (cfg->checkpoint_every < 1) return set_error(OIM_E_ARG, "checkpoint_every must be >= 1");
+    if (cfg->flags != 0) return set_error(OIM_E_ARG, "flags must be 0");
+    if (p->dense) return set_error(OIM_E_UNSUPPORTED, "the adjoint runs on sparse problems");
+    if (p->max_inst_n > kAdjMaxN)
+        return set_error(OIM_E_UNSUPPORTED, "adjoint: an instance has more than 4096 oscillators");
+    if ((int64_t)cfg->R * p->n_inst > (int64_t)INT32_MAX / 2)
+        return set_error(OIM_E_ARG, "R * instances too large");
     return OIM_OK;
 }
 

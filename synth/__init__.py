@@ -145,6 +145,20 @@ def planted_batch(count: int, n_lo: int, n_hi: int, avg_degree: float, q: int, s
             for g, nv in enumerate(sizes)]
 
 
+def block_diagonal(graphs):
+    """One CSR holding several graphs as disjoint diagonal blocks, and the
+    instance offsets (graph b owns nodes off[b] .. off[b+1]-1)."""
+    off = np.cumsum([0] + [g.n for g in graphs]).astype(np.int32)
+    ei, ej, w = [], [], []
+    for g, o in zip(graphs, off[:-1]):
+        a, b, c = g.upper_edges()
+        ei.append(a + o)
+        ej.append(b + o)
+        w.append(c)
+    return csr_from_edges(int(off[-1]), np.concatenate(ei), np.concatenate(ej),
+                          np.concatenate(w)), off
+
+
 def sk_dense(n: int, seed: int) -> np.ndarray:
     """Sherrington-Kirkpatrick coupling: J_ij = z / sqrt(n), z ~ N(0,1) drawn in
     FP64 for i < j, mirrored, zero diagonal, stored as FP32 [n][n]."""

@@ -33,3 +33,10 @@ def c1_graph():
 def c2_graph():
     """Sparse max-cut at scale: 100x100 torus, +-1 weights, seed 1."""
     return synth.torus(100, 100, seed=1, signed=True)
+
+
+def c5_batch(count=128, n=2000, avg_degree=10.0):
+    """Adjoint schedule-tuning workload: `count` graphs G(n, p = d/(n-1)) with
+    +-1 weights (graph g drawn with seed 4 + g), as one block-diagonal batch."""
+    gs = [synth.gnp_avg_degree(n, avg_degree, seed=4 + g, signed=True) for g in range(count)]
+    return synth.block_diagonal(gs)

@@ -151,3 +151,17 @@ def test_block_batch_validation(oim):
     assert call([0, 5, 10]) == 2           # an edge crosses the boundary
     assert call([0, 6, 6, 10]) == 1        # empty instance
     assert call([1, 6, 10]) == 1           # does not start at 0
+
+
+def test_adjoint_entry_points_reject_bad_handles(oim):
+    # host-side checks run before any device call
+    from paper_2505_22631_amd import _lib
+    L = oim.lib()
+    cfg = _lib.AdjointCfg(2, 1, 10, 0.01, 4, 0)
+    words = ctypes.c_int64(-1)
+    assert L.oim_adjoint_checkpoint_words(None, ctypes.byref(cfg), ctypes.byref(words)) == 8
+    assert L.oim_adjoint_forward(None, ctypes.byref(cfg), None, None, None, None, 0, None, None,
+                                 None, None, None) == 8
+    assert L.oim_adjoint_backward(None, ctypes.byref(cfg), None, None, None, None, 0, None, None,
+                                  None, None, None) == 8
+    assert "destroyed" in L.oim_last_error().decode()

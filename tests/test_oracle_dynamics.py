@@ -168,16 +168,7 @@ def test_resume_and_replica_independence(orc):
 
 
 def _concat(graphs):
-    """Block-diagonal CSR of several graphs and the instance offsets."""
-    off = np.cumsum([0] + [g.n for g in graphs]).astype(np.int32)
-    ei, ej, w = [], [], []
-    for g, o in zip(graphs, off[:-1]):
-        a, b, c = g.upper_edges()
-        ei.append(a + o)
-        ej.append(b + o)
-        w.append(c)
-    return synth.csr_from_edges(int(off[-1]), np.concatenate(ei), np.concatenate(ej),
-                                np.concatenate(w)), off
+    return synth.block_diagonal(graphs)
 
 
 def test_block_batch_instances(orc):
@@ -234,4 +225,37 @@ def test_adjoint_matches_finite_differences(orc, q):
             args_up = [up if v is vec else v for v in (K, Ks, sg)]
             args_dn = [dn if v is vec else v for v in (K, Ks, sg)]
             fd = (loss(*args_up) - loss(*args_dn)) / (2 * eps)
+            assert grad[s] == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+def test_adjoint_block_batch_matches_finite_differences(orc):
+    # the batched adjoint (noise per instance) against central differences of
+    # the block-diagonal forward integrator, and its loss against the relaxed
+    # cut of that integrator's final phases
+    gs = [synth.random_small(n, 0.45, seed=30 + n, weights="pm1") for n in (7, 11)]
+    big, off = _concat(gs)
+    J = -big.w.astype(np.float64)
+    steps, dt = 20, 0.02
+    K = synth.ramp(0.3, 1.2, steps).astype(np.float64)
+    Ks = synth.ramp(0.0, 1.5, steps).astype(np.float64)
+    sg = synth.const(0.2, steps).astype(np.float64)
+    th0 = synth.theta0(2, big.n, seed=4).astype(np.float64)
+    sd = synth.seeds(2, 8)
+
+    def loss(K_, Ks_, sg_):
+        th = orc.run_csr_blocks(big.row_ptr, big.col, J, off, th0, q=2, dt=dt, K=K_, Ks=Ks_,
+                                sigma=sg_, seeds=sd, step0=3)
+        return orc.relaxed_cut(big.row_ptr, big.col, J, th)
+
+    L, gK, gKs, gS = orc.adjoint_csr(big.row_ptr, big.col, J, th0, q=2, dt=dt, K=K, Ks=Ks,
+                                     sigma=sg, seeds=sd, step0=3, inst_off=off)
+    assert L == pytest.approx(loss(K, Ks, sg), rel=1e-12)
+    eps = 1e-5
+    for s in (0, 11, 19):
+        for vec, grad in ((K, gK), (Ks, gKs), (sg, gS)):
+            up, dn = vec.copy(), vec.copy()
+            up[s] += eps
+            dn[s] -= eps
+            fd = (loss(*[up if v is vec else v for v in (K, Ks, sg)]) -
+                  loss(*[dn if v is vec else v for v in (K, Ks, sg)])) / (2 * eps)
             assert grad[s] == pytest.approx(fd, rel=1e-5, abs=1e-9)
