@@ -60,14 +60,25 @@ __device__ __forceinline__ int swz(int row, int seg) {
     return row * (kTK * 2) + ((seg ^ ((row >> 1) & (kSegs - 1))) << 4);
 }
 
+// Operands live in HBM as tiled images of what one stage puts in LDS, so that
+// every DMA instruction of a wave moves 1 KiB of contiguous memory:
+//   J: block (row tile ti, stage kc) of 16 KiB at (ti * nk + kc) * 16 KiB,
+//      J_hi rows then J_lo rows (kA bytes each);
+//   X: block (replica tile tr, stage kc) of 16 KiB at (tr * nk + kc) * 16 KiB,
+//      components S_hi, S_lo, C_hi, C_lo (kB bytes each).
+// Inside a block a row of kTK = 32 elements is 64 bytes, segments swizzled
+// exactly as in LDS.  Byte offset of element (row rr, column kk) of a region:
+__device__ __forceinline__ int tile_off(int rr, int kk) {
+    return swz(rr, kk >> 3) + (kk & 7) * 2;
+}
+
 struct DenseArgs {
-    const uint16_t* Jhi;   // [np][np]
-    const uint16_t* Jlo;
-    const uint16_t* Xin;   // [4][Rp][np]: S_hi, S_lo, C_hi, C_lo
-    uint16_t* Xout;
+    const unsigned char* Jt;   // tiled J_hi / J_lo, np x np each
+    const unsigned char* Xin;  // tiled X = [S | C] split, Rp x np x 4 components
+    unsigned char* Xout;
     uint32_t* U;           // [Rp][np] phase words
     const uint64_t* seeds;
-    int np, Rp, n, R, q;
+    int np, Rp, n, R, q, nk;
     float kc, ks, ns;      // step coefficients in 2^-32-turn units (unused for init)
     const float* K;
     const float* Ks;
@@ -84,6 +95,7 @@ constexpr int kRow = kTK * 2;              // bytes per LDS row
 constexpr int kA = kTM * kRow;             // one A matrix per stage
 constexpr int kB = kTR * kRow;             // one B component per stage
 constexpr int kWaveChunks = kStageBytes / 1024 / (kTB / 64);  // 1 KiB DMA chunks per wave per stage
+constexpr int kBlock = kStageBytes / 2;    // bytes of one tiled J or X block (one stage)
 
 // s_waitcnt immediate that waits until at most `n` vector-memory operations
 // of this wave are outstanding (lgkm and exp counters left at their maxima).
@@ -94,9 +106,13 @@ __device__ __forceinline__ constexpr int vmcnt_imm(int n) {
 // Barrier that completes this wave's LDS reads and nothing else: the DMA
 // loads of later stages stay in flight (a workgroup fence, as in
 // __syncthreads, would wait for every outstanding vector-memory operation).
-// The memory clobber keeps the compiler from moving LDS accesses across it.
+// The wait is a builtin so the compiler's own counter bookkeeping sees it; the
+// empty asm statements keep memory accesses from moving across the barrier.
 __device__ __forceinline__ void lds_barrier() {
-    asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0), vmcnt and expcnt at their maxima
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
 }
 
 // One 256-thread workgroup per CU (one wave per SIMD).  Stages move from
@@ -116,28 +132,18 @@ void dense_step_kernel(DenseArgs a) {
     const int np = a.np, Rp = a.Rp;
     const size_t plane = (size_t)Rp * np;
 
-    // Chunk c of a stage (16 rows x 64 bytes) sits at LDS bytes 1024c: chunks
-    // 0-7 are J_hi rows, 8-15 J_lo rows, 16-31 the four X components (4 chunks
-    // each).  Wave w moves chunks 8w..8w+7; lane l lands on row l/4 of the
-    // chunk, slot l%4, which holds logical segment (l%4) ^ ((row>>1)&3).
-    const int lrow = lane >> 2, lseg = (lane & 3) ^ ((lrow >> 1) & (kSegs - 1));
-    const uint16_t* src[kWaveChunks];
-#pragma unroll
-    for (int x = 0; x < kWaveChunks; ++x) {
-        const int c = wave * kWaveChunks + x;
-        if (c < 16) {
-            const int row = (c & 7) * 16 + lrow;
-            src[x] = (c < 8 ? a.Jhi : a.Jlo) + (size_t)(i0 + row) * np + lseg * 8;
-        } else {
-            const int comp = (c - 16) >> 2, row = ((c - 16) & 3) * 16 + lrow;
-            src[x] = a.Xin + comp * plane + (size_t)(r0 + row) * np + lseg * 8;
-        }
-    }
-    auto issue = [&](int kc) __attribute__((always_inline)) {
-        unsigned char* dst = lds[kc % kDepth] + wave * kWaveChunks * 1024;
+    // Chunk c of a stage (1 KiB) sits at LDS bytes 1024c: chunks 0-15 are the
+    // J block of the stage, 16-31 the X block.  Wave w moves chunks
+    // 8w..8w+7, lane l the 16 bytes at 16l of each.
+    const unsigned char* src = wave < 2
+        ? a.Jt + (size_t)blockIdx.x * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
+        : a.Xin + (size_t)blockIdx.y * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
+    auto issue = [&](int kc, int buf) __attribute__((always_inline)) {
+        unsigned char* dst = lds[buf] + wave * kWaveChunks * 1024;
+        const unsigned char* sp = src + (size_t)kc * kBlock;
 #pragma unroll
         for (int x = 0; x < kWaveChunks; ++x)
-            __builtin_amdgcn_global_load_lds((glb_void_t*)(src[x] + (size_t)kc * kTK),
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(sp + x * 1024),
                                              (lds_void_t*)(dst + x * 1024), 16, 0, 0);
     };
 
@@ -147,51 +153,105 @@ void dense_step_kernel(DenseArgs a) {
 #pragma unroll
         for (int c = 0; c < 2; ++c) acc[b][c][0] = acc[b][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-    const int nk = np / kTK;  // at least kDepth (np is a multiple of 128)
+    const int nk = np / kTK;  // a multiple of 4 (np is a multiple of 128)
     const int frow = lane & 15, fseg = lane >> 4;
-#pragma unroll
-    for (int d = 0; d < kDepth - 1; ++d) issue(d);
-    for (int kc = 0; kc < nk; ++kc) {
-        // stage kc has landed once at most (stages issued after it) x chunks
-        // of this wave's DMA loads are outstanding
-        const int ahead = nk - 1 - kc < kDepth - 2 ? nk - 1 - kc : kDepth - 2;
-        if (ahead == kDepth - 2) __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 2) * kWaveChunks));
-        else if (ahead == 1) __builtin_amdgcn_s_waitcnt(vmcnt_imm(kWaveChunks));
-        else __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
-        // all waves' chunks of stage kc are in LDS, and every wave is done
-        // reading the buffer that stage kc + kDepth - 1 overwrites
-        lds_barrier();
-        if (kc + kDepth - 1 < nk) issue(kc + kDepth - 1);
-        const unsigned char* base = lds[kc % kDepth];
-        bf16x8 bh[2][2], bl[2][2];  // [replica block][S, C]
+
+    // MFMA operand fragments of one stage: lane l holds row l%16 of each
+    // 16-row block at K offsets 8(l/16)..8(l/16)+7.
+    struct Frags {
+        bf16x8 ah[4], al[4];          // J_hi, J_lo of the wave's 4 row blocks
+        bf16x8 bh[2][2], bl[2][2];    // X_hi, X_lo [replica block][S, C]
+    };
+    auto read_frags = [&](const unsigned char* base, Frags& f) __attribute__((always_inline)) {
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
             const int row = wn * 32 + cb * 16 + frow;
 #pragma unroll
             for (int sc = 0; sc < 2; ++sc) {
                 const unsigned char* bb = base + 2 * kA + (2 * sc) * kB;
-                bh[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + swz(row, fseg));
-                bl[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + kB + swz(row, fseg));
+                f.bh[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + swz(row, fseg));
+                f.bl[cb][sc] = *reinterpret_cast<const bf16x8*>(bb + kB + swz(row, fseg));
             }
         }
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int row = wm * 64 + b * 16 + frow;
-            const bf16x8 ah = *reinterpret_cast<const bf16x8*>(base + swz(row, fseg));
-            const bf16x8 al = *reinterpret_cast<const bf16x8*>(base + kA + swz(row, fseg));
-#pragma unroll
-            for (int cb = 0; cb < 2; ++cb) {
-#pragma unroll
-                for (int sc = 0; sc < 2; ++sc) {
-                    f32x4 c = acc[b][cb][sc];
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh[cb][sc], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl[cb][sc], c, 0, 0, 0);
-                    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh[cb][sc], c, 0, 0, 0);
-                    acc[b][cb][sc] = c;
-                }
-            }
+            f.ah[b] = *reinterpret_cast<const bf16x8*>(base + swz(row, fseg));
+            f.al[b] = *reinterpret_cast<const bf16x8*>(base + kA + swz(row, fseg));
         }
+    };
+    // the three split products of one accumulator are 16 MFMAs apart, so no
+    // MFMA waits for the result of the one before it
+    auto mfmas = [&](const Frags& f) __attribute__((always_inline)) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int sc = 0; sc < 2; ++sc)
+                        acc[b][cb][sc] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            p == 2 ? f.al[b] : f.ah[b], p == 1 ? f.bl[cb][sc] : f.bh[cb][sc],
+                            acc[b][cb][sc], 0, 0, 0);
+    };
+    // One stage kc < nk - 1: its fragments were requested a stage earlier
+    // (cur).  After the barrier stage kc + 1 is readable and the buffer of
+    // stage kc - 1 is free: the DMA of stage kc + kDepth - 1 (clamped to the
+    // last stage near the end, which only refills a buffer nobody reads
+    // again), the fragment reads of stage kc + 1 and the MFMAs of stage kc are
+    // interleaved so that neither the DMA queue nor LDS holds up the matrix
+    // cores.
+    auto stage = [&](int kc, Frags& cur, Frags& nxt) __attribute__((always_inline)) {
+        // stages 0 .. kc + kDepth - 2 are issued; stage kc + 1 has landed
+        // when only the kDepth - 3 stages after it are outstanding
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 3) * kWaveChunks));
+        lds_barrier();
+        // the reads come first in program order: the compiler cannot tell the
+        // DMA's LDS target from the buffer being read and keeps that order
+        read_frags(lds[(kc + 1) % kDepth], nxt);
+        issue(kc + kDepth - 1 < nk ? kc + kDepth - 1 : nk - 1, (kc + kDepth - 1) % kDepth);
+        mfmas(cur);
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // DS read
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);  // MFMA
+        }
+#pragma unroll
+        for (int i = 0; i < kWaveChunks; ++i) {
+            __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);  // VMEM (DMA)
+            __builtin_amdgcn_sched_group_barrier(0x008, 3, 0);  // MFMA
+        }
+    };
+
+#pragma unroll
+    for (int d = 0; d < kDepth - 1; ++d) issue(d, d);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 2) * kWaveChunks));
+    lds_barrier();
+    Frags F0, F1;
+    read_frags(lds[0], F0);
+    for (int kc = 0; kc < nk - 2; kc += 2) {
+        stage(kc, F0, F1);
+        stage(kc + 1, F1, F0);
     }
+    stage(nk - 2, F0, F1);
+    // The epilogue's phase words and keys are requested in one batch before
+    // the last stage's MFMAs, so their latency overlaps them (U is padded to
+    // Rp x np, so every quad's load is in bounds).
+    const int qi0 = i0 + wm * 64 + 4 * (lane >> 4);  // first row of the quads of block b = 0
+    uint4 uq[2][4];
+    uint64_t seedv[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
+        seedv[cb] = r < a.R ? a.seeds[r] : 0ull;
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            uq[cb][b] = *reinterpret_cast<const uint4*>(a.U + (size_t)r * np + qi0 + b * 16);
+    }
+    mfmas(F1);
+    // the refills issued by the last stages land before the LDS is released
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
 
     // ---- epilogue: SHIL, noise, Euler-Maruyama update, next split X ----
     const float kcoef = a.kc, kscoef = a.ks, nscoef = a.ns;
@@ -199,14 +259,12 @@ void dense_step_kernel(DenseArgs a) {
     for (int cb = 0; cb < 2; ++cb) {
         const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
         const bool rvalid = r < a.R;
-        const uint64_t seed = rvalid ? a.seeds[r] : 0ull;
-        const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+        const uint32_t k0 = (uint32_t)seedv[cb], k1 = (uint32_t)(seedv[cb] >> 32);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-            const int i = i0 + wm * 64 + b * 16 + 4 * (lane >> 4);  // first row of the quad
+            const int i = qi0 + b * 16;  // first row of the quad
             if (!rvalid || i >= a.n) continue;
-            uint4 u4 = *reinterpret_cast<const uint4*>(a.U + (size_t)r * np + i);
-            uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+            uint32_t u[4] = {uq[cb][b].x, uq[cb][b].y, uq[cb][b].z, uq[cb][b].w};
             float z[4];
             normals4((uint32_t)(i >> 2), a.t, 0u, k0, k1, z);
             uint16_t shi[4], slo[4], chi[4], clo[4];
@@ -222,14 +280,15 @@ void dense_step_kernel(DenseArgs a) {
                 split_bf16(c1, chi[x], clo[x]);
             }
             *reinterpret_cast<uint4*>(a.U + (size_t)r * np + i) = uint4{u[0], u[1], u[2], u[3]};
-            const size_t off = (size_t)r * np + i;
-            *reinterpret_cast<uint2*>(a.Xout + 0 * plane + off) =
+            unsigned char* xo = a.Xout + ((size_t)(r >> 6) * a.nk + (i >> 5)) * kBlock +
+                                tile_off(r & 63, i & 31);
+            *reinterpret_cast<uint2*>(xo + 0 * kB) =
                 uint2{shi[0] | ((uint32_t)shi[1] << 16), shi[2] | ((uint32_t)shi[3] << 16)};
-            *reinterpret_cast<uint2*>(a.Xout + 1 * plane + off) =
+            *reinterpret_cast<uint2*>(xo + 1 * kB) =
                 uint2{slo[0] | ((uint32_t)slo[1] << 16), slo[2] | ((uint32_t)slo[3] << 16)};
-            *reinterpret_cast<uint2*>(a.Xout + 2 * plane + off) =
+            *reinterpret_cast<uint2*>(xo + 2 * kB) =
                 uint2{chi[0] | ((uint32_t)chi[1] << 16), chi[2] | ((uint32_t)chi[3] << 16)};
-            *reinterpret_cast<uint2*>(a.Xout + 3 * plane + off) =
+            *reinterpret_cast<uint2*>(xo + 3 * kB) =
                 uint2{clo[0] | ((uint32_t)clo[1] << 16), clo[2] | ((uint32_t)clo[3] << 16)};
         }
     }
@@ -239,9 +298,11 @@ void dense_step_kernel(DenseArgs a) {
 // ping-pong sets; padding rows and replicas get X = 0 in both (they add
 // nothing to any coupling sum and the step kernel never writes them).
 __global__ __launch_bounds__(256) void dense_init_kernel(const float* theta, const uint32_t* phase,
-                                                         uint32_t* U, uint16_t* X, uint16_t* X2,
-                                                         int n, int R, int np, int Rp) {
+                                                         uint32_t* U, unsigned char* X,
+                                                         unsigned char* X2, int n, int R, int np,
+                                                         int Rp) {
     const size_t plane = (size_t)Rp * np;
+    const int nk = np / kTK;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
          e += (size_t)gridDim.x * blockDim.x) {
         const int r = (int)(e / np), i = (int)(e % np);
@@ -257,10 +318,13 @@ __global__ __launch_bounds__(256) void dense_init_kernel(const float* theta, con
         uint16_t sh, sl, ch, cl;
         split_bf16(s, sh, sl);
         split_bf16(c, ch, cl);
-        X[e] = X2[e] = sh;
-        X[plane + e] = X2[plane + e] = sl;
-        X[2 * plane + e] = X2[2 * plane + e] = ch;
-        X[3 * plane + e] = X2[3 * plane + e] = cl;
+        const size_t o = ((size_t)(r >> 6) * nk + (i >> 5)) * kBlock + tile_off(r & 63, i & 31);
+        const uint16_t v[4] = {sh, sl, ch, cl};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            *reinterpret_cast<uint16_t*>(X + o + k * kB) = v[k];
+            *reinterpret_cast<uint16_t*>(X2 + o + k * kB) = v[k];
+        }
     }
 }
 
@@ -276,18 +340,20 @@ __global__ __launch_bounds__(256) void dense_final_kernel(const uint32_t* U, flo
     }
 }
 
-// J -> (J_hi, J_lo) with the diagonal and the padding zeroed.
-__global__ __launch_bounds__(256) void dense_split_kernel(const float* J, uint16_t* hi, uint16_t* lo,
-                                                          int n, int np) {
+// J -> tiled (J_hi, J_lo) with the diagonal and the padding zeroed.
+__global__ __launch_bounds__(256) void dense_split_kernel(const float* J, unsigned char* Jt, int n,
+                                                          int np) {
     const size_t total = (size_t)np * np;
+    const int nk = np / kTK;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int i = (int)(e / np), j = (int)(e % np);
         const float v = (i < n && j < n && i != j) ? J[(size_t)i * n + j] : 0.f;
         uint16_t h, l;
         split_bf16(v, h, l);
-        hi[e] = h;
-        lo[e] = l;
+        const size_t o = ((size_t)(i / kTM) * nk + j / kTK) * kBlock + tile_off(i % kTM, j % kTK);
+        *reinterpret_cast<uint16_t*>(Jt + o) = h;
+        *reinterpret_cast<uint16_t*>(Jt + o + kA) = l;
     }
 }
 
@@ -361,12 +427,11 @@ int dense_prepare(Problem* p, const float* J) {
     if ((st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jdense), bytes, "dense J"))) return st;
     hipError_t e = hipMemcpy(p->d_Jdense, J, bytes, hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_error(e, "upload dense J");
-    const size_t pb = (size_t)np * np * sizeof(uint16_t);
-    if ((st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jhi), pb, "J_hi")) ||
-        (st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jlo), pb, "J_lo")))
+    const size_t pb = (size_t)np * np * 2 * sizeof(uint16_t);
+    if ((st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jtiled), pb, "tiled J")))
         return st;
-    hipLaunchKernelGGL(dense_split_kernel, dim3(4096), dim3(256), 0, 0, p->d_Jdense, p->d_Jhi,
-                       p->d_Jlo, n, np);
+    hipLaunchKernelGGL(dense_split_kernel, dim3(4096), dim3(256), 0, 0, p->d_Jdense, p->d_Jtiled,
+                       n, np);
     if ((st = check_launch("dense_split_kernel"))) return st;
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_error(e, "dense split");
@@ -375,10 +440,9 @@ int dense_prepare(Problem* p, const float* J) {
 
 void dense_release(Problem* p) {
     hipFree(p->d_Jdense);
-    hipFree(p->d_Jhi);
-    hipFree(p->d_Jlo);
+    hipFree(p->d_Jtiled);
     p->d_Jdense = nullptr;
-    p->d_Jhi = p->d_Jlo = nullptr;
+    p->d_Jtiled = nullptr;
 }
 
 int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
@@ -405,8 +469,8 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     }
     unsigned char* w = static_cast<unsigned char*>(p->d_work);
     uint32_t* U = reinterpret_cast<uint32_t*>(w);
-    uint16_t* X0 = reinterpret_cast<uint16_t*>(w + plane * 4);
-    uint16_t* X1 = X0 + 4 * plane;
+    unsigned char* X0 = w + plane * 4;
+    unsigned char* X1 = X0 + 4 * plane * 2;
     double* H = reinterpret_cast<double*>(w + plane * 4 + 2 * 4 * plane * 2);
     double* btmp = H + R;
     int32_t* bstep = reinterpret_cast<int32_t*>(btmp + R);
@@ -418,8 +482,8 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     StepFn fn = cfg->q == 2 ? dense_step_kernel<2> : cfg->q == 3 ? dense_step_kernel<3>
                                                                    : dense_step_kernel<0>;
     DenseArgs a{};
-    a.Jhi = p->d_Jhi;
-    a.Jlo = p->d_Jlo;
+    a.Jt = p->d_Jtiled;
+    a.nk = np / kTK;
     a.U = U;
     a.seeds = seeds;
     a.np = np;

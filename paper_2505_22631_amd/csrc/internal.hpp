@@ -68,8 +68,7 @@ struct Problem {
 
     // device: dense coupling (dense problems), FP32 and the BF16 split
     float* d_Jdense = nullptr;
-    uint16_t* d_Jhi = nullptr;
-    uint16_t* d_Jlo = nullptr;
+    unsigned char* d_Jtiled = nullptr;  // J_hi / J_lo in per-stage tiles
 
     // cached workspace for the stepwise / dense loops
     void* d_work = nullptr;
