@@ -67,21 +67,24 @@ def _schedules(wl, max_row_sum, steps, dt):
     return K, Ks, synth.const(wl["sigma"], steps), kmax, ksmax
 
 
-KERNEL_SOURCES = ["paper_2505_22631_amd/csrc/sparse_persistent.hip",
+SPARSE_SOURCES = ["paper_2505_22631_amd/csrc/sparse_persistent.hip",
                   "paper_2505_22631_amd/csrc/noise.hpp", "paper_2505_22631_amd/csrc/phase.hpp"]
-PROFILE = "profiles/persistent_sparse_kernel__torus100x100_R256.md"
+SPARSE_PROFILE = "profiles/persistent_sparse_kernel__torus100x100_R256.md"
+DENSE_SOURCES = ["paper_2505_22631_amd/csrc/dense.hip", "paper_2505_22631_amd/csrc/noise.hpp",
+                 "paper_2505_22631_amd/csrc/phase.hpp"]
+DENSE_PROFILE = "profiles/dense_step_kernel__sk4096_R512.md"
 
 
-def _measured_traffic():
-    """HBM bytes per launch from the committed counter summary, if it was taken
+def _measured_traffic(profile, sources):
+    """HBM bytes per launch from a committed counter summary, if it was taken
     on the kernel sources as they are now (else None)."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     try:
-        for line in open(os.path.join(ROOT, PROFILE)):
+        for line in open(os.path.join(ROOT, profile)):
             if line.startswith("traffic_bytes_per_launch:"):
                 parts = line.split()
                 if parts[3] == h.hexdigest()[:16]:
@@ -146,11 +149,11 @@ def bench_dense(args):
     J = synth.sk_dense(n, seed=3)
     dev = torch.device("cuda:0")
     prob = oim.Problem.from_dense(J)
-    kmax = 2.0 * 0.5 / (dt * prob.info["max_abs_row_sum"])
-    ksmax = 0.5 / (dt * q)
-    K = torch.from_numpy(synth.ramp(0.0, kmax, steps)).to(dev)
-    Ks = torch.from_numpy(synth.triangle(ksmax, 5, steps)).to(dev)
-    sg = torch.from_numpy(synth.const(0.1, steps)).to(dev)
+    # frozen from a K x Ks x shape sweep on 128 replicas (mean best energy):
+    # the Gershgorin bound is loose for SK couplings, so K_max is 32 times it
+    wl = dict(q=q, k_mul=32.0, ks_mul=0.03, ks_shape="ramp", periods=0, sigma=0.1)
+    Kh, Ksh, sgh, kmax, ksmax = _schedules(wl, prob.info["max_abs_row_sum"], steps, dt)
+    K, Ks, sg = (torch.from_numpy(x).to(dev) for x in (Kh, Ksh, sgh))
     th_init = torch.from_numpy(synth.theta0(R, n, seed=100)).to(dev)
     seeds = torch.from_numpy(synth.seeds(R, 0)).to(dev)
     theta = torch.empty_like(th_init)
@@ -195,9 +198,211 @@ def bench_dense(args):
                    "n": n, "replicas": R, "em_steps": steps, "K_max": kmax, "Ks_max": ksmax},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
-                     "traffic": None, "kernel": "dense_step_kernel (per run, incl. epilogue)",
+                     "traffic": _measured_traffic(DENSE_PROFILE, DENSE_SOURCES),
+                     "kernel": "dense_step_kernel (per run, incl. epilogue)",
                      "run_ms": run_ms, "flops_per_step": flops_step},
         "best_energy_per_spin": e_per_spin,
+    }
+    print(json.dumps(out))
+    prob.close()
+
+
+def _sync_time(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fn()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0
+
+
+def bench_colouring(args):
+    """Batched Potts 3-colouring: 1024 planted 3-colourable graphs, n uniform in
+    [100, 600] (seed 2), average degree 4.6, J = -1, q = 3, one replica per
+    graph (seed = graph index), 5000 steps, readout every 50 steps; all graphs
+    in one launch of the LDS-resident kernel against a plain loop of one launch
+    per graph.  Target: >= 99 % satisfied edges in every graph."""
+    import torch
+    import paper_2505_22631_amd as oim
+    import synth
+    count, steps, q, M = 1024, 5000, 3, 50
+    dt = float(np.float32(0.01))
+    graphs = [g for g, _ in synth.planted_batch(count, 100, 600, 4.6, q, seed=2)]
+    big, off = synth.block_diagonal(graphs)
+    dev = torch.device("cuda:0")
+    prob = oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col,
+                                       -np.ones(big.nnz, np.float32), off)
+    # frozen from a K x Ks x sigma x waveform sweep on this batch (graphs at 99 %)
+    wl = dict(q=q, k_mul=4.0, ks_mul=0.5, ks_shape="triangle", periods=10, sigma=0.2)
+    K, Ks, sg, kmax, ksmax = _schedules(wl, prob.info["max_abs_row_sum"], steps, dt)
+    dK, dKs, dsg = (torch.from_numpy(x).to(dev) for x in (K, Ks, sg))
+    th_init = torch.from_numpy(synth.theta0(1, big.n, seed=100)).to(dev)
+    seeds = torch.from_numpy(synth.seeds(1, 0)).to(dev)
+    theta = torch.empty_like(th_init)
+    nr = oim.n_readouts(steps, M)
+    trace = torch.empty((nr, count), dtype=torch.float64, device=dev)
+    best_h = torch.empty(count, dtype=torch.float64, device=dev)
+    best_step = torch.empty(count, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream()
+    edges = np.array([g.nnz // 2 for g in graphs], np.float64)
+    target = np.floor(0.01 * edges)  # conflicts allowed per graph
+
+    def solve(ev=None):
+        theta.copy_(th_init)
+        if ev:
+            ev[0].record(stream)
+        oim.oim_run(prob.handle, big.n, theta, dK, dKs, dsg, seeds, q=q, dt=dt, readout_every=M,
+                    trace=trace, best_h=best_h, best_step=best_step)
+        if ev:
+            ev[1].record(stream)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        solve(evs[k])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    run_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    ms_per_step = wall / args.steps * 1e3
+    eu = float(big.nnz) * steps
+    tr = trace.cpu().numpy()                                   # conflicts per readout
+    best_so_far = np.minimum.accumulate(tr, axis=0)            # [readouts][graphs]
+    ok = best_so_far <= target[None, :]
+    reached = ok[-1]
+    first = np.where(reached, np.argmax(ok, axis=0), -1)
+    t99 = (float(first.max() + 1) * M / steps * run_ms) if reached.all() else None
+
+    # plain loop over a sample of the graphs (one problem, one launch each)
+    sample = min(args.plain_graphs, count)
+    rng = np.random.default_rng(5)
+    pick = np.sort(rng.choice(count, size=sample, replace=False))
+    per, hit_ms, sat = [], [], []
+    tr1 = torch.empty((nr, 1), dtype=torch.float64, device=dev)
+    for b in pick:
+        g = graphs[b]
+        with oim.Problem.from_csr(g.n, g.row_ptr, g.col, -np.ones(g.nnz, np.float32)) as p1:
+            th1 = th_init[:, off[b]:off[b + 1]].contiguous()
+            sd1 = torch.from_numpy(synth.seeds(1, 0)).to(dev)
+            oim.oim_run(p1.handle, g.n, th1.clone(), dK, dKs, dsg, sd1, q=q, dt=dt)  # warm
+            th1c = th1.clone()
+
+            def one():
+                oim.oim_run(p1.handle, g.n, th1c, dK, dKs, dsg, sd1, q=q, dt=dt,
+                            readout_every=M, trace=tr1)
+            el = _sync_time(one)
+        per.append(el)
+        c = np.minimum.accumulate(tr1[:, 0].cpu().numpy())
+        h = np.nonzero(c <= target[b])[0]
+        sat.append(bool(h.size))
+        hit_ms.append((min((int(h[0]) + 1) * M, steps) / steps * el * 1e3) if h.size else None)
+    plain_ms_per_graph = float(np.mean(per)) * 1e3 if per else None
+    plain_total_ms = plain_ms_per_graph * count if per else None
+    plain_t99 = (float(np.mean([x for x in hit_ms if x is not None])) * count
+                 if per and all(sat) else None)
+    out = {
+        "metric": "edge-updates/s & time-to-99%-best-cut, batched vs plain, 1 MI355X",
+        "value": eu / (ms_per_step * 1e-3), "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched Potts 3-colouring: 1024 planted graphs, n in [100,600], "
+                               "avg degree 4.6, one launch", "graphs": count, "n_total": big.n,
+                   "nnz": big.nnz, "em_steps": steps, "q": q, "K_max": kmax, "Ks_max": ksmax,
+                   "readout_every": M},
+        "kernel_ms": run_ms,
+        "time_to_99pct_satisfied_all_graphs_ms": t99,
+        "graphs_reaching_99pct": int(reached.sum()),
+        "plain": {"ms_per_graph": plain_ms_per_graph, "total_ms_extrapolated": plain_total_ms,
+                  "time_to_99pct_all_graphs_ms_extrapolated": plain_t99,
+                  "graphs_timed": sample,
+                  "eu_per_s": eu / (plain_total_ms * 1e-3) if per else None},
+    }
+    print(json.dumps(out))
+    prob.close()
+
+
+def bench_adjoint(args):
+    """Adjoint schedule tuning: 128 graphs G(2000, 10/1999) with +-1 weights
+    (graph g with seed 4 + g) in one block-diagonal batch, one replica each,
+    2000 steps with fixed Philox noise, checkpoints every 64 steps; gradient of
+    the relaxed cut with respect to the per-step K, Ks and sigma.  Forward and
+    backward (with recomputation) are timed separately, and against a plain
+    loop of one adjoint per graph."""
+    import torch
+    import paper_2505_22631_amd as oim
+    import synth
+    count, n, steps, C, q = 128, 2000, 2000, 64, 2
+    dt = float(np.float32(0.01))
+    graphs = [synth.gnp_avg_degree(n, 10.0, seed=4 + g, signed=True) for g in range(count)]
+    big, off = synth.block_diagonal(graphs)
+    dev = torch.device("cuda:0")
+    prob = oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, (-big.w).astype(np.float32),
+                                       off)
+    wl = dict(q=q, k_mul=2.0, ks_mul=1.0, ks_shape="triangle", periods=5, sigma=0.1)
+    K, Ks, sg, kmax, ksmax = _schedules(wl, prob.info["max_abs_row_sum"], steps, dt)
+    dK, dKs, dsg = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in (K, Ks, sg))
+    th0 = torch.from_numpy(synth.theta0(1, big.n, seed=100)).to(dev)
+    seeds = torch.from_numpy(synth.seeds(1, 0)).to(dev)
+    words = oim.oim_adjoint_checkpoint_words(prob.handle, q=q, R=1, steps=steps, dt=dt,
+                                             checkpoint_every=C)
+    ckpt = torch.empty(words, dtype=torch.uint32, device=dev)
+    loss = torch.empty(count, dtype=torch.float64, device=dev)
+    g3 = [torch.empty(steps, dtype=torch.float64, device=dev) for _ in range(3)]
+
+    def fwd():
+        oim.oim_adjoint_forward(prob.handle, big.n, th0, dK, dKs, dsg, seeds, ckpt, q=q, dt=dt,
+                                checkpoint_every=C, loss=loss)
+
+    def bwd():
+        oim.oim_adjoint_backward(prob.handle, 1, dK, dKs, dsg, seeds, ckpt, *g3, q=q, dt=dt,
+                                 checkpoint_every=C)
+
+    for _ in range(args.warmup):
+        fwd()
+        bwd()
+    tf = [_sync_time(fwd) for _ in range(args.steps)]
+    tb = [_sync_time(bwd) for _ in range(args.steps)]
+    t_f, t_b = float(np.median(tf)), float(np.median(tb))
+    eu = float(big.nnz) * steps
+    # plain: one problem and one adjoint per graph, a sample of them
+    sample = min(args.plain_graphs, count)
+    per = []
+    for b in range(sample):
+        g = graphs[b]
+        with oim.Problem.from_csr(g.n, g.row_ptr, g.col, (-g.w).astype(np.float32)) as p1:
+            w1 = oim.oim_adjoint_checkpoint_words(p1.handle, q=q, R=1, steps=steps, dt=dt,
+                                                  checkpoint_every=C)
+            ck1 = torch.empty(w1, dtype=torch.uint32, device=dev)
+            t1 = th0[:, off[b]:off[b + 1]].contiguous()
+            h1 = [torch.empty(steps, dtype=torch.float64, device=dev) for _ in range(3)]
+
+            def one():
+                oim.oim_adjoint_forward(p1.handle, g.n, t1, dK, dKs, dsg, seeds, ck1, q=q, dt=dt,
+                                        checkpoint_every=C)
+                oim.oim_adjoint_backward(p1.handle, 1, dK, dKs, dsg, seeds, ck1, *h1, q=q,
+                                         dt=dt, checkpoint_every=C)
+            one()
+            per.append(_sync_time(one))
+    plain_ms = float(np.mean(per)) * 1e3 * count if per else None
+    out = {
+        "metric": "edge-updates/s & time-to-99%-best-cut, batched vs plain, 1 MI355X",
+        "value": 3.0 * eu / ((t_f + t_b)), "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": (t_f + t_b) * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "adjoint schedule gradient: 128 x G(2000, 10/1999) +-1, one launch",
+                   "graphs": count, "n_total": big.n, "nnz": big.nnz, "em_steps": steps,
+                   "checkpoint_every": C, "K_max": kmax, "Ks_max": ksmax,
+                   "edge_updates_counted": "forward 1x, backward (recompute + adjoint) 2x"},
+        "forward_ms": t_f * 1e3, "backward_ms": t_b * 1e3,
+        "loss": float(loss.sum().item()),
+        "grad_norms": [float(x.norm().item()) for x in g3],
+        "plain": {"ms_total_extrapolated": plain_ms, "graphs_timed": sample,
+                  "speedup_batched": plain_ms / ((t_f + t_b) * 1e3) if per else None},
     }
     print(json.dumps(out))
     prob.close()
@@ -213,6 +418,8 @@ def main():
     ap.add_argument("--plain", type=int, default=8,
                     help="replicas to time in the plain one-launch-per-replica loop")
     ap.add_argument("--dense-steps", type=int, default=1000)
+    ap.add_argument("--plain-graphs", type=int, default=32,
+                    help="graphs timed in the plain per-graph loop of the batched workloads")
     ap.add_argument("--ref-mult", type=int, default=10,
                     help="length multiple of the untimed reference run that sets best_ref")
     args = ap.parse_args()
@@ -224,6 +431,10 @@ def main():
 
     if args.workload == "sk4096":
         return bench_dense(args)
+    if args.workload == "colouring":
+        return bench_colouring(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
 
     import torch
     import paper_2505_22631_amd as oim
@@ -328,7 +539,8 @@ def main():
     achieved = bytes_per_step * steps / (kern_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": _measured_traffic() if args.workload == "torus" else None,
+                "traffic": (_measured_traffic(SPARSE_PROFILE, SPARSE_SOURCES)
+                            if args.workload == "torus" else None),
                 "kernel": "persistent_sparse_kernel", "kernel_ms": kern_ms,
                 "bytes_per_em_step": bytes_per_step}
     out = {

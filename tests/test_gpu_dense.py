@@ -105,3 +105,29 @@ def test_dense_rejects_fp32_precision(oim):
         with pytest.raises(oim.OimError):
             oim.run(prob, t, z, z, z, torch.zeros(1, dtype=torch.uint64, device="cuda"), q=2,
                     dt=DT)
+
+
+def test_dense_full_size_sampled_replicas(oim, orc):
+    # the n = 4096, 512-replica SK workload in the benchmark's launch
+    # configuration (32 x 8 workgroups); replicas are independent, so two of
+    # them (first and last) are checked against the oracle over 10 steps of the
+    # benchmark's schedule, the others must stay finite and in [0, 2pi)
+    n, R, steps = 4096, 512, 10
+    J = synth.sk_dense(n, seed=3)
+    with oim.Problem.from_dense(J) as prob:
+        kmax = 32.0 * 0.5 / (DT * prob.info["max_abs_row_sum"])
+        K = synth.ramp(0.0, kmax, 1000)[:steps].copy()
+        Ks = synth.ramp(0.0, 0.03 * 0.5 / (DT * 2), 1000)[:steps].copy()
+        sg = synth.const(0.1, steps)
+        th0 = synth.theta0(R, n, seed=100)
+        sd = synth.seeds(R, 0)
+        got, _ = _run(oim, prob, th0, K, Ks, sg, sd, 2)
+    pick = [0, R - 1]
+    want = orc.run_dense(J.astype(np.float64), th0[pick], q=2, dt=DT, K=K, Ks=Ks, sigma=sg,
+                         seeds=sd[pick], nthreads=2)
+    err = wrapdiff(got[pick], want).max()
+    bound = _bf16x3_bound(J.astype(np.float64), K, steps)
+    print(f"dense n=4096 R=512 replicas {pick}: max |dtheta| = {err:.3e} rad "
+          f"(split bound {bound:.2e})", flush=True)
+    assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+    assert err < max(1e-5, 20 * bound)
