@@ -119,6 +119,7 @@ typedef struct {
     int32_t n_instances;       /* instances of a block-diagonal batch (else 1)      */
     double max_abs_row_sum;    /* max_i sum_j |J_ij| (Gershgorin bound of J)         */
     double sum_J_upper;        /* sum_{i<j} J_ij; max-cut total weight W = -this     */
+    int32_t max_instance_n;    /* oscillators of the largest instance (n if one)    */
 } oim_problem_info;
 
 /* Fills *info (host memory).  Synchronous, no device work. */
@@ -179,6 +180,44 @@ typedef struct {
 int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
             const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
             uint32_t* phase, const oim_readout* readout, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Launch-shape autotuning of the LDS-resident loop (the per-thread batch of
+ * oscillators of Sec. III-C, chosen by measurement).  A launch variant is a
+ * workgroup size (64 ... 1024 threads) and a number of 64-quad slices per
+ * wave; any variant gives bit-identical results, only the speed differs.
+ * ---------------------------------------------------------------------- */
+#define OIM_TUNE_MAX 48
+typedef struct {
+    int32_t n_tried;                          /* variants timed (<= OIM_TUNE_MAX listed) */
+    int32_t chosen_block;                     /* threads per workgroup of the winner */
+    int32_t chosen_slices_per_wave;
+    float chosen_ms;                          /* its trial time */
+    int32_t block[OIM_TUNE_MAX];              /* every variant tried, in order */
+    int32_t slices_per_wave[OIM_TUNE_MAX];
+    float ms[OIM_TUNE_MAX];                   /* best of two timings, milliseconds */
+} oim_tune_report;
+
+/* Times every launch variant that covers the problem's largest instance on
+ * the first trial_steps steps of the given schedules (device arrays of at
+ * least trial_steps entries; seeds [R]; theta [R][n] device, read only: the
+ * trials run on a scratch copy, without readout) and keeps the fastest for
+ * later oim_run calls on p with the same SHIL order class (q = 2, q = 3,
+ * other).  cfg gives q, R, dt; its steps must be >= trial_steps >= 1.
+ * report may be NULL.  Synchronous (waits for the trials on stream).
+ * Allocates and frees a scratch copy of theta.  Errors: OIM_E_ARG,
+ * OIM_E_UNSUPPORTED (dense problem, or a replica that does not fit the
+ * LDS-resident loop), OIM_E_NOMEM, OIM_E_HIP. */
+int oim_autotune(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                 const float* sigma, const uint64_t* seeds, const float* theta,
+                 int32_t trial_steps, oim_tune_report* report, hipStream_t stream);
+
+/* Sets the launch variant for SHIL order q's class directly (a choice cached
+ * from an earlier oim_autotune on a problem of the same shape); block = 0
+ * returns to the default choice.  Errors: OIM_E_ARG (q out of range, no
+ * such variant, or one whose waves do not cover the largest instance),
+ * OIM_E_UNSUPPORTED (dense problem). */
+int oim_set_tuning(oim_problem p, int32_t q, int32_t block, int32_t slices_per_wave);
 
 /* Phase words <-> radians for count elements (device arrays):
  * phase = rint(frac(theta / 2pi) * 2^32) mod 2^32 (FP64), and

@@ -27,7 +27,8 @@ __all__ = [
     "OIM_PREC_BF16X3", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
     "oim_problem_from_csr_blocks", "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
     "oim_round", "oim_cut", "oim_conflicts", "oim_energy", "oim_phase_from_theta",
-    "oim_theta_from_phase", "oim_adjoint_checkpoint_words", "oim_adjoint_forward",
+    "oim_theta_from_phase", "oim_autotune", "oim_set_tuning",
+    "oim_adjoint_checkpoint_words", "oim_adjoint_forward",
     "oim_adjoint_backward", "run", "n_readouts",
 ]
 
@@ -147,6 +148,32 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
                         _dev(theta, torch.float32, None, "theta"),
                         _dev(phase, torch.uint32, (R, n), "phase", True), ctypes.byref(ro),
                         _stream(stream)))
+
+
+def oim_autotune(h, n, theta, K, Ks, sigma, seeds, *, q, dt, trial_steps, stream=None) -> dict:
+    """Time every launch variant of the LDS-resident loop on trial_steps steps
+    (theta[R][n] is read, not modified) and keep the fastest for this problem
+    and SHIL order; returns the report as a dict."""
+    if theta.dim() != 2 or theta.shape[1] != n:
+        raise ValueError("theta must be [R][n]")
+    R = int(theta.shape[0])
+    steps = int(K.shape[0])
+    cfg = RunCfg(int(q), R, steps, float(dt), 0, 0)
+    rep = _lib.TuneReport()
+    check(lib().oim_autotune(h, ctypes.byref(cfg), _dev(K, torch.float32, (steps,), "K"),
+                             _dev(Ks, torch.float32, (steps,), "Ks"),
+                             _dev(sigma, torch.float32, (steps,), "sigma"),
+                             _dev(seeds, torch.uint64, (R,), "seeds"),
+                             _dev(theta, torch.float32, None, "theta"), int(trial_steps),
+                             ctypes.byref(rep), _stream(stream)))
+    k = rep.n_tried
+    return {"block": rep.chosen_block, "slices_per_wave": rep.chosen_slices_per_wave,
+            "ms": rep.chosen_ms,
+            "tried": [(rep.block[i], rep.slices_per_wave[i], rep.ms[i]) for i in range(k)]}
+
+
+def oim_set_tuning(h, q, block, slices_per_wave) -> None:
+    check(lib().oim_set_tuning(h, int(q), int(block), int(slices_per_wave)))
 
 
 def _adj_cfg(q, R, steps, dt, checkpoint_every):

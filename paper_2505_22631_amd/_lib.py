@@ -32,10 +32,19 @@ class AdjointCfg(ctypes.Structure):
                 ("checkpoint_every", _i32), ("flags", _u32)]
 
 
+OIM_TUNE_MAX = 48
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("n_tried", _i32), ("chosen_block", _i32), ("chosen_slices_per_wave", _i32),
+                ("chosen_ms", _f32), ("block", _i32 * OIM_TUNE_MAX),
+                ("slices_per_wave", _i32 * OIM_TUNE_MAX), ("ms", _f32 * OIM_TUNE_MAX)]
+
+
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", _i32), ("is_dense", _i32), ("nnz", _i64), ("integer_weights", _i32),
                 ("n_instances", _i32), ("max_abs_row_sum", ctypes.c_double),
-                ("sum_J_upper", ctypes.c_double)]
+                ("sum_J_upper", ctypes.c_double), ("max_instance_n", _i32)]
 
 
 # every symbol declared in include/oim.h, with its ctypes prototype
@@ -57,6 +66,9 @@ PROTOTYPES = {
     "oim_cut": (ctypes.c_int, [_P, _i32, _P, _P, _P, _P]),
     "oim_conflicts": (ctypes.c_int, [_P, _i32, _P, _P, _P]),
     "oim_energy": (ctypes.c_int, [_P, _i32, _i32, _P, _P, _P, _P, _P]),
+    "oim_autotune": (ctypes.c_int, [_P, ctypes.POINTER(RunCfg), _P, _P, _P, _P, _P, _i32,
+                                    ctypes.POINTER(TuneReport), _P]),
+    "oim_set_tuning": (ctypes.c_int, [_P, _i32, _i32, _i32]),
     "oim_adjoint_checkpoint_words": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg),
                                                     ctypes.POINTER(_i64)]),
     "oim_adjoint_forward": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg), _P, _P, _P, _P, _i64,

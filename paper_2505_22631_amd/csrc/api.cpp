@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "internal.hpp"
@@ -216,6 +217,7 @@ __attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
     info->n_instances = p->n_inst;
     info->max_abs_row_sum = p->max_abs_row_sum;
     info->sum_J_upper = p->sum_J_upper;
+    info->max_instance_n = p->dense ? p->n : p->max_inst_n;
     return OIM_OK;
 }
 
@@ -251,6 +253,47 @@ __attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_
         return launch_persistent_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro,
                                         stream);
     return launch_stepwise_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
+}
+
+__attribute__((visibility("default"))) int oim_autotune(oim_problem h, const oim_run_cfg* cfg,
+                                                        const float* K, const float* Ks,
+                                                        const float* sigma,
+                                                        const uint64_t* seeds, const float* theta,
+                                                        int32_t trial_steps,
+                                                        oim_tune_report* report,
+                                                        hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    int st = validate_cfg(p, cfg);
+    if (st) return st;
+    if (p->dense) return set_error(OIM_E_UNSUPPORTED, "autotuning applies to sparse problems");
+    if (trial_steps < 1 || trial_steps > cfg->steps)
+        return set_error(OIM_E_ARG, "trial_steps must be in [1, cfg->steps]");
+    if (!K || !Ks || !sigma || !seeds || !theta) return set_error(OIM_E_ARG, "NULL array");
+    if ((st = check_device(p))) return st;
+    return tune_persistent(p, cfg, K, Ks, sigma, seeds, theta, trial_steps, report, stream);
+}
+
+__attribute__((visibility("default"))) int oim_set_tuning(oim_problem h, int32_t q, int32_t block,
+                                                          int32_t slices_per_wave) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    if (q < 2 || q > kMaxQ) return set_error(OIM_E_ARG, "q must be in [2, 16]");
+    if (p->dense) return set_error(OIM_E_UNSUPPORTED, "tuning applies to sparse problems");
+    const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
+    if (block == 0) {
+        p->tuned_tb[qc] = p->tuned_ms[qc] = 0;
+        return OIM_OK;
+    }
+    if (!persistent_variant_fits(p, block, slices_per_wave))
+        return set_error(OIM_E_ARG, "no launch variant (" + std::to_string(block) + ", " +
+                                        std::to_string(slices_per_wave) +
+                                        ") covering the largest instance");
+    p->tuned_tb[qc] = (int16_t)block;
+    p->tuned_ms[qc] = (int16_t)slices_per_wave;
+    return OIM_OK;
 }
 
 __attribute__((visibility("default"))) int oim_adjoint_checkpoint_words(oim_problem h,

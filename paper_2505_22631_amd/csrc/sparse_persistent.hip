@@ -299,7 +299,13 @@ struct Variant {
         }                                                                                \
     }
 
+// Block sizes from one wave up: the small ones suit batches of small
+// instances (fewer idle lanes, cheap barriers); the autotuner times them all.
 const Variant kVariants[] = {
+    OIM_VARIANT(64, 1),   OIM_VARIANT(64, 2),   OIM_VARIANT(64, 3),   OIM_VARIANT(64, 4),
+    OIM_VARIANT(64, 6),   OIM_VARIANT(64, 8),
+    OIM_VARIANT(128, 1),  OIM_VARIANT(128, 2),  OIM_VARIANT(128, 3),  OIM_VARIANT(128, 4),
+    OIM_VARIANT(128, 6),  OIM_VARIANT(128, 8),
     OIM_VARIANT(256, 1),  OIM_VARIANT(256, 2),  OIM_VARIANT(256, 3),  OIM_VARIANT(256, 4),
     OIM_VARIANT(256, 6),  OIM_VARIANT(256, 8),  OIM_VARIANT(256, 10), OIM_VARIANT(256, 12),
     OIM_VARIANT(512, 1),  OIM_VARIANT(512, 2),  OIM_VARIANT(512, 3),  OIM_VARIANT(512, 4),
@@ -320,13 +326,14 @@ size_t lds_bytes(int plane, int tb) {
 
 constexpr uint64_t kMaxSellBytes = 0x7fffffffull;
 
-// Pick the variant: fewest waves that still cover every slice with the
-// registers of one variant, preferring 8 waves per workgroup.
+// Default choice without tuning: fewest waves that still cover every slice
+// with the registers of one variant, preferring 8 waves per workgroup, among
+// blocks of at least 256 threads.
 const Variant* pick_variant(int S, int tb_hint) {
     const Variant* best = nullptr;
     for (const Variant& v : kVariants) {
         const int W = v.tb / 64;
-        if (tb_hint && v.tb != tb_hint) continue;
+        if (tb_hint ? v.tb != tb_hint : v.tb < 256) continue;
         if (W * v.ms < S) continue;
         if (!best) { best = &v; continue; }
         // smallest ms*W (least idle), then the preferred block size
@@ -342,7 +349,32 @@ int env_int(const char* name, int dflt) {
     return v ? atoi(v) : dflt;
 }
 
+const Variant* find_variant(int tb, int ms) {
+    for (const Variant& v : kVariants)
+        if (v.tb == tb && v.ms == ms) return &v;
+    return nullptr;
+}
+
+int q_class(int q) { return q == 2 ? 1 : q == 3 ? 2 : 0; }
+
+// The variant a run uses: the tuned one for this SHIL order if set, else an
+// OIM_PERSIST_TB block-size hint, else the default choice.
+const Variant* run_variant(const Problem* p, int q) {
+    const int qc = q_class(q);
+    if (p->tuned_tb[qc]) {
+        const Variant* v = find_variant(p->tuned_tb[qc], p->tuned_ms[qc]);
+        if (v) return v;
+    }
+    const Variant* v = pick_variant(p->max_slices, env_int("OIM_PERSIST_TB", 0));
+    return v ? v : pick_variant(p->max_slices, 0);
+}
+
 }  // namespace
+
+bool persistent_variant_fits(const Problem* p, int tb, int ms) {
+    const Variant* v = find_variant(tb, ms);
+    return v && (tb / 64) * ms >= p->max_slices;
+}
 
 bool persistent_sparse_fits(const Problem* p) {
     if (p->dense || p->max_slices == 0) return false;
@@ -351,13 +383,13 @@ bool persistent_sparse_fits(const Problem* p) {
     return pick_variant(p->max_slices, 0) != nullptr;
 }
 
-int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,
-                             const float* Ks, const float* sigma, const uint64_t* seeds,
-                             int64_t step0, float* theta, uint32_t* phase,
-                             const oim_readout* ro, hipStream_t stream) {
+namespace {
+int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                   const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                   uint32_t* phase, const oim_readout* ro, hipStream_t stream,
+                   const Variant* forced) {
     const int S = p->max_slices;
-    const Variant* v = pick_variant(S, env_int("OIM_PERSIST_TB", 0));
-    if (!v) v = pick_variant(S, 0);
+    const Variant* v = forced ? forced : run_variant(p, cfg->q);
     if (!v || !persistent_sparse_fits(p))
         return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
     PersistArgs a{};
@@ -396,6 +428,92 @@ int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const flo
     hipLaunchKernelGGL(fn, dim3(cfg->R * p->n_inst), dim3(v->tb), lds, stream, a);
     e = hipGetLastError();
     if (e != hipSuccess) return hip_error(e, "persistent_sparse_kernel launch");
+    return OIM_OK;
+}
+}  // namespace
+
+int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,
+                             const float* Ks, const float* sigma, const uint64_t* seeds,
+                             int64_t step0, float* theta, uint32_t* phase,
+                             const oim_readout* ro, hipStream_t stream) {
+    return launch_variant(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, nullptr);
+}
+
+// Autotuner: every variant whose waves cover the largest instance runs the
+// first trial_steps steps of the caller's schedule on a scratch copy of
+// theta (no readout), twice; the faster of the two timings (HIP events on the
+// caller's stream) ranks it.  The winner is recorded in the problem for this
+// SHIL order.  Results do not depend on the variant: every oscillator's
+// arithmetic is the same in all of them.
+int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                    const float* sigma, const uint64_t* seeds, const float* theta,
+                    int32_t trial_steps, oim_tune_report* rep, hipStream_t stream) {
+    if (!persistent_sparse_fits(p))
+        return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
+    const size_t bytes = (size_t)cfg->R * p->n * sizeof(float);
+    float* scratch = nullptr;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&scratch), bytes);
+    if (e != hipSuccess) {
+        return e == hipErrorOutOfMemory ? set_error(OIM_E_NOMEM, "autotune scratch: out of device memory")
+                                        : hip_error(e, "autotune scratch");
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int st = OIM_OK;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess)
+        st = hip_error(e, "autotune events");
+    oim_run_cfg c = *cfg;
+    c.steps = trial_steps;
+    c.readout_every = 0;
+    const Variant* best = nullptr;
+    float best_ms = 0.f;
+    int tried = 0;
+    for (const Variant& v : kVariants) {
+        if (st) break;
+        if ((v.tb / 64) * v.ms < p->max_slices) continue;
+        float t_min = 0.f;
+        for (int rep_i = 0; rep_i < 2 && !st; ++rep_i) {
+            if ((e = hipMemcpyAsync(scratch, theta, bytes, hipMemcpyDeviceToDevice, stream)) != hipSuccess ||
+                (e = hipEventRecord(e0, stream)) != hipSuccess) {
+                st = hip_error(e, "autotune copy");
+                break;
+            }
+            st = launch_variant(p, &c, K, Ks, sigma, seeds, 0, scratch, nullptr, nullptr, stream, &v);
+            if (st) break;
+            float ms = 0.f;
+            if ((e = hipEventRecord(e1, stream)) != hipSuccess ||
+                (e = hipEventSynchronize(e1)) != hipSuccess ||
+                (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) {
+                st = hip_error(e, "autotune timing");
+                break;
+            }
+            if (rep_i == 0 || ms < t_min) t_min = ms;
+        }
+        if (st) break;
+        if (rep && tried < OIM_TUNE_MAX) {
+            rep->block[tried] = v.tb;
+            rep->slices_per_wave[tried] = v.ms;
+            rep->ms[tried] = t_min;
+        }
+        ++tried;
+        if (!best || t_min < best_ms) {
+            best = &v;
+            best_ms = t_min;
+        }
+    }
+    if (e0) hipEventDestroy(e0);
+    if (e1) hipEventDestroy(e1);
+    hipFree(scratch);
+    if (st) return st;
+    if (!best) return set_error(OIM_E_UNSUPPORTED, "no variant covers the largest instance");
+    const int qc = q_class(cfg->q);
+    p->tuned_tb[qc] = (int16_t)best->tb;
+    p->tuned_ms[qc] = (int16_t)best->ms;
+    if (rep) {
+        rep->n_tried = tried < OIM_TUNE_MAX ? tried : OIM_TUNE_MAX;
+        rep->chosen_block = best->tb;
+        rep->chosen_slices_per_wave = best->ms;
+        rep->chosen_ms = best_ms;
+    }
     return OIM_OK;
 }
 

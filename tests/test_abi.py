@@ -165,3 +165,13 @@ def test_adjoint_entry_points_reject_bad_handles(oim):
     assert L.oim_adjoint_backward(None, ctypes.byref(cfg), None, None, None, None, 0, None, None,
                                   None, None, None) == 8
     assert "destroyed" in L.oim_last_error().decode()
+
+
+def test_tuning_entry_points_reject_bad_handles(oim):
+    from paper_2505_22631_amd import _lib
+    L = oim.lib()
+    cfg = _lib.RunCfg(2, 1, 10, 0.01, 0, 0)
+    rep = _lib.TuneReport()
+    assert L.oim_autotune(None, ctypes.byref(cfg), None, None, None, None, None, 5,
+                          ctypes.byref(rep), None) == 8
+    assert L.oim_set_tuning(None, 2, 64, 1) == 8

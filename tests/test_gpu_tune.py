@@ -1,0 +1,100 @@
+"""GPU tests of the launch-shape autotuner of the LDS-resident loop: every
+variant gives the same bits, the tuner keeps one that exists, and the cache
+applies a stored choice without re-measuring."""
+import numpy as np
+import pytest
+
+import synth
+from _util import DT, ramp_schedule
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def oim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_22631_amd as m
+    m.lib()
+    return m
+
+
+def _setup(oim, graphs, R, steps, q, seed=0):
+    import torch
+    big, off = synth.block_diagonal(graphs)
+    prob = oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col,
+                                       -np.ones(big.nnz, np.float32), off)
+    K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, steps)
+    dev = torch.device("cuda:0")
+    t = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    th0 = t(synth.theta0(R, big.n, seed=seed))
+    return prob, big, t(K), t(Ks), t(sg), t(synth.seeds(R, 3)), th0
+
+
+def _run(oim, prob, th0, K, Ks, sg, sd, q, M=0):
+    import torch
+    th = th0.clone()
+    out = oim.run(prob, th, K, Ks, sg, sd, q=q, dt=DT, readout_every=M)
+    torch.cuda.synchronize()
+    return th.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_every_variant_gives_identical_bits(oim):
+    graphs = [synth.planted_colouring(nv, 4.6, 3, seed=nv)[0] for nv in (90, 700, 260, 33)]
+    prob, big, K, Ks, sg, sd, th0 = _setup(oim, graphs, 2, 120, 3)
+    ref, ro_ref = _run(oim, prob, th0, K, Ks, sg, sd, 3, M=40)
+    slices = -(-(-(-max(g.n for g in graphs) // 4)) // 64)
+    checked = 0
+    for block in (64, 128, 256, 512, 1024):
+        for spw in (1, 2, 3, 4, 6, 8):
+            if (block // 64) * spw < slices:
+                continue
+            try:
+                oim.oim_set_tuning(prob.handle, 3, block, spw)
+            except oim.OimError:
+                continue  # not a compiled variant
+            got, ro = _run(oim, prob, th0, K, Ks, sg, sd, 3, M=40)
+            np.testing.assert_array_equal(got, ref, err_msg=f"variant ({block}, {spw})")
+            np.testing.assert_array_equal(ro["trace"], ro_ref["trace"])
+            checked += 1
+    assert checked >= 8
+    prob.close()
+
+
+def test_autotune_keeps_a_variant_and_leaves_theta(oim):
+    import torch
+    graphs = [synth.planted_colouring(nv, 4.6, 3, seed=nv)[0] for nv in (150, 400, 600)]
+    prob, big, K, Ks, sg, sd, th0 = _setup(oim, graphs, 4, 300, 3)
+    before = th0.clone()
+    ref, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
+    rep = oim.oim_autotune(prob.handle, big.n, th0, K, Ks, sg, sd, q=3, dt=DT, trial_steps=50)
+    torch.cuda.synchronize()
+    assert torch.equal(th0, before)
+    assert len(rep["tried"]) >= 5
+    assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in rep["tried"]]
+    assert rep["ms"] == min(ms for _, _, ms in rep["tried"]) > 0
+    got, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
+    np.testing.assert_array_equal(got, ref)
+    with pytest.raises(oim.OimError, match="variant"):
+        oim.oim_set_tuning(prob.handle, 3, 64, 1)  # one wave cannot cover 3 slices
+    with pytest.raises(oim.OimError, match="trial_steps"):
+        oim.oim_autotune(prob.handle, big.n, th0, K, Ks, sg, sd, q=3, dt=DT, trial_steps=301)
+    prob.close()
+
+
+def test_tune_cache_roundtrip(oim, tmp_path, monkeypatch):
+    from paper_2505_22631_amd import tune
+    monkeypatch.setenv("OIM_TUNE_CACHE", str(tmp_path / "cache.json"))
+    graphs = [synth.planted_colouring(nv, 4.6, 3, seed=nv)[0] for nv in (120, 300)]
+    prob, big, K, Ks, sg, sd, th0 = _setup(oim, graphs, 2, 200, 3)
+    e1, measured1 = tune.tuned(prob, th0, K, Ks, sg, sd, q=3, dt=DT, trial_steps=40)
+    assert measured1
+    prob2, *_ = _setup(oim, graphs, 2, 200, 3, seed=5)
+    e2, measured2 = tune.tuned(prob2, th0, K, Ks, sg, sd, q=3, dt=DT)
+    assert not measured2 and (e2["block"], e2["slices_per_wave"]) == (e1["block"], e1["slices_per_wave"])
+    ref, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
+    got, _ = _run(oim, prob2, th0, K, Ks, sg, sd, 3)
+    np.testing.assert_array_equal(got, ref)
+    prob.close()
+    prob2.close()
