@@ -120,11 +120,35 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     double best = DBL_MAX;
     int32_t best_at = -1;
 
+    // Schedules arrive 64 steps at a time, one step per lane, with the next
+    // chunk's vector loads in flight while the current chunk is used; each
+    // step reads its three values with v_readlane, so no step waits on a
+    // scalar load.
+    auto sched = [&](const float* v, int c) {
+        const int i = c * 64 + lane;
+        return i < a.steps ? v[i] : 0.0f;
+    };
+    float cK = sched(a.K, 0), cKs = sched(a.Ks, 0), cS = sched(a.sigma, 0);
+    float nK = sched(a.K, 1), nKs = sched(a.Ks, 1), nS = sched(a.sigma, 1);
+
     for (int s = 0; s < a.steps; ++s) {
         const uint32_t t = (uint32_t)(a.step0 + s);
-        const float kc = -a.dt * a.K[s] * kTurnScale;
-        const float ks = -a.dt * a.Ks[s] * kTurnScale;
-        const float ns = a.sigma[s] * sqrt_dt * kTurnScale;
+        if (s > 0 && (s & 63) == 0) {
+            cK = nK;
+            cKs = nKs;
+            cS = nS;
+            const int c = (s >> 6) + 1;
+            nK = sched(a.K, c);
+            nKs = sched(a.Ks, c);
+            nS = sched(a.sigma, c);
+        }
+        const int sl = s & 63;
+        const float Kt = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cK), sl));
+        const float Kst = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cKs), sl));
+        const float St = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(cS), sl));
+        const float kc = -a.dt * Kt * kTurnScale;
+        const float ks = -a.dt * Kst * kTurnScale;
+        const float ns = St * sqrt_dt * kTurnScale;
 
         // ---- phase A: coupling sums over the sliced-ELL rows ----
         // 4 edges of each of the slice's 4 rows per iteration: 8 16-byte
