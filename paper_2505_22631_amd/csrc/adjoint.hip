@@ -45,11 +45,14 @@ namespace {
 constexpr int kAdjTB = 512;
 constexpr int kAdjWaves = kAdjTB / 64;
 constexpr int kAdjQPT = kAdjMaxN / 4 / kAdjTB;  // quads per thread at the size limit
+constexpr int kCsrGlobal = 0, kCsrLdsUnit = 1, kCsrLds = 2;
 
 struct AdjArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const float* J;
+    int tabN;              // table length in LDS (largest instance, rounded up to 4)
+    int64_t max_nnz;       // most stored entries of one instance
     const int4* inst;      // per instance: first slice, slices, first oscillator, size
     int I, n_total, P;     // instances, oscillators, padded words per replica
     int R, q, steps, C, nseg;
@@ -105,18 +108,52 @@ __device__ __forceinline__ size_t slot_index(const AdjArgs& a, const Ctx& x, int
     return ((size_t)slot * a.R + x.r) * a.P + x.base + i;
 }
 
+// Where a workgroup reads its instance's CSR rows.  CSR_LDS: copies in LDS
+// made at kernel start (row offsets relative to the instance, 16-bit local
+// column indices, and either FP32 weights or, with UNIT, the sign of a
+// unit weight in the index's top bit); otherwise the global CSR through L2.
+template <int MODE>
+struct Rows {
+    const AdjArgs* a;
+    int off;
+    const int32_t* rp;    // LDS row offsets [nb + 1]
+    const uint16_t* col;  // LDS column indices
+    const float* w;       // LDS weights (MODE == kCsrLds)
+    __device__ __forceinline__ int64_t begin(int i) const {
+        return MODE == kCsrGlobal ? a->row_ptr[off + i] : (int64_t)rp[i];
+    }
+    __device__ __forceinline__ int64_t end(int i) const {
+        return MODE == kCsrGlobal ? a->row_ptr[off + i + 1] : (int64_t)rp[i + 1];
+    }
+    __device__ __forceinline__ void edge(int64_t e, int& j, float& wt) const {
+        if constexpr (MODE == kCsrGlobal) {
+            j = a->col[e] - off;
+            wt = a->J[e];
+        } else if constexpr (MODE == kCsrLdsUnit) {
+            const uint32_t c = col[e];
+            j = (int)(c & 0x7fffu);
+            wt = (c & 0x8000u) ? -1.0f : 1.0f;
+        } else {
+            j = col[e];
+            wt = w[e];
+        }
+    }
+};
+
 // Gather over the CSR row of local oscillator i from an LDS table of
 // (s, c, s lam, c lam): A = sum J c_j, B = sum J s_j and, if LAM,
 // Cl = sum J c_j lam_j, Dl = sum J s_j lam_j.
-template <bool LAM>
-__device__ __forceinline__ void gather(const AdjArgs& a, const Ctx& x, const float4* tab, int i,
+template <bool LAM, int MODE>
+__device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, int i,
                                        float& A, float& B, float& Cl, float& Dl) {
-    const int64_t e0 = a.row_ptr[x.off + i], e1 = a.row_ptr[x.off + i + 1];
+    const int64_t e0 = g.begin(i), e1 = g.end(i);
     float A0 = 0.f, B0 = 0.f, C0 = 0.f, D0 = 0.f, A1 = 0.f, B1 = 0.f, C1 = 0.f, D1 = 0.f;
     int64_t e = e0;
     for (; e + 2 <= e1; e += 2) {
-        const int j0 = a.col[e] - x.off, j1 = a.col[e + 1] - x.off;
-        const float w0 = a.J[e], w1 = a.J[e + 1];
+        int j0, j1;
+        float w0, w1;
+        g.edge(e, j0, w0);
+        g.edge(e + 1, j1, w1);
         if constexpr (LAM) {
             const float4 p0 = tab[j0], p1 = tab[j1];
             A0 = __builtin_fmaf(w0, p0.y, A0);
@@ -137,8 +174,9 @@ __device__ __forceinline__ void gather(const AdjArgs& a, const Ctx& x, const flo
         }
     }
     if (e < e1) {
-        const int j0 = a.col[e] - x.off;
-        const float w0 = a.J[e];
+        int j0;
+        float w0;
+        g.edge(e, j0, w0);
         if constexpr (LAM) {
             const float4 p0 = tab[j0];
             A0 = __builtin_fmaf(w0, p0.y, A0);
@@ -171,9 +209,10 @@ __device__ __forceinline__ void put_sc(const Ctx& x, float4* tab, const uint32_t
 
 // One synchronous Euler-Maruyama step of the thread's oscillators reading
 // neighbour (s, c) from tin and writing the new (s, c) into tout.
-template <int QM>
-__device__ __forceinline__ void fwd_step(const AdjArgs& a, const Ctx& x, int s, const float4* tin,
-                                         float4* tout, uint32_t (&u)[kAdjQPT][4]) {
+template <int QM, int MODE>
+__device__ __forceinline__ void fwd_step(const AdjArgs& a, const Ctx& x, const Rows<MODE>& g, int s,
+                                         const float4* tin, float4* tout,
+                                         uint32_t (&u)[kAdjQPT][4]) {
     const int q = QM ? QM : a.q;
     const uint32_t t = (uint32_t)(a.step0 + s);
     const float kc = -a.dt * a.K[s] * kTurnScale;
@@ -190,7 +229,7 @@ __device__ __forceinline__ void fwd_step(const AdjArgs& a, const Ctx& x, int s, 
             const int i = 4 * m + j;
             if (i >= x.nb) break;
             float A, B, Cl, Dl;
-            gather<false>(a, x, tin, i, A, B, Cl, Dl);
+            gather<false>(g, tin, i, A, B, Cl, Dl);
             const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
             const float coup = __builtin_fmaf(si, A, -(ci * B));
             const float drift = __builtin_fmaf(kc, coup, ks * sin_q<QM>(si, ci, u[k][j], q));
@@ -231,11 +270,49 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-template <int QM>
+// Dynamic LDS: two tables of tabN float4, then (CSR in LDS) the instance's
+// row offsets, 16-bit column indices and FP32 weights.  Fills the CSR copy.
+template <int MODE>
+__device__ __forceinline__ Rows<MODE> setup_rows(const AdjArgs& a, const Ctx& x, unsigned char* smem) {
+    Rows<MODE> g;
+    g.a = &a;
+    g.off = x.off;
+    unsigned char* p = smem + (size_t)32 * a.tabN;
+    g.rp = reinterpret_cast<const int32_t*>(p);
+    int32_t* rp = reinterpret_cast<int32_t*>(p);
+    p += ((size_t)4 * (a.tabN + 1) + 15) & ~(size_t)15;
+    uint16_t* col = reinterpret_cast<uint16_t*>(p);
+    g.col = col;
+    p += ((size_t)2 * a.max_nnz + 15) & ~(size_t)15;
+    float* w = reinterpret_cast<float*>(p);
+    g.w = w;
+    if constexpr (MODE != kCsrGlobal) {
+        const int64_t e0 = a.row_ptr[x.off];
+        const int64_t ne = a.row_ptr[x.off + x.nb] - e0;
+        for (int i = threadIdx.x; i <= x.nb; i += kAdjTB)
+            rp[i] = (int32_t)(a.row_ptr[x.off + i] - e0);
+        for (int64_t e = threadIdx.x; e < ne; e += kAdjTB) {
+            const uint32_t c = (uint32_t)(a.col[e0 + e] - x.off);
+            const float wt = a.J[e0 + e];
+            if constexpr (MODE == kCsrLdsUnit) {
+                col[e] = (uint16_t)(c | (wt < 0.0f ? 0x8000u : 0u));
+            } else {
+                col[e] = (uint16_t)c;
+                w[e] = wt;
+            }
+        }
+    }
+    return g;
+}
+
+template <int QM, int MODE>
 __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
-    __shared__ float4 tab[2][kAdjMaxN];
+    extern __shared__ __align__(16) unsigned char smem[];
     __shared__ double red[kAdjWaves];
     const Ctx x = make_ctx(a);
+    const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
+    float4* const tabs = reinterpret_cast<float4*>(smem);
+    auto tab = [&](int k) { return tabs + (size_t)k * a.tabN; };
     uint32_t u[kAdjQPT][4];
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k)
@@ -244,15 +321,15 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
             const int i = 4 * (threadIdx.x + k * kAdjTB) + j;
             u[k][j] = i < x.nb ? phase_from_theta(a.theta0[(size_t)x.r * a.n_total + x.off + i]) : 0u;
         }
-    put_sc(x, tab[0], u);
+    put_sc(x, tab(0), u);
     __syncthreads();
     for (int s = 0; s < a.steps; ++s) {
         if (s % a.C == 0) store_words(a, x, a.ckpt, s / a.C, u);
-        fwd_step<QM>(a, x, s, tab[s & 1], tab[(s + 1) & 1], u);
+        fwd_step<QM>(a, x, g, s, tab(s & 1), tab((s + 1) & 1), u);
         __syncthreads();
     }
     // relaxed cut of the final phases: sum_i (c_i A_i + s_i B_i - sum_j J_ij) / 4
-    const float4* fin = tab[a.steps & 1];
+    const float4* fin = tab(a.steps & 1);
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k) {
@@ -263,9 +340,14 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
             const int i = 4 * m + j;
             if (i >= x.nb) break;
             float A, B, Cl, Dl;
-            gather<false>(a, x, fin, i, A, B, Cl, Dl);
+            gather<false>(g, fin, i, A, B, Cl, Dl);
             double rs = 0.0;
-            for (int64_t e = a.row_ptr[x.off + i]; e < a.row_ptr[x.off + i + 1]; ++e) rs += (double)a.J[e];
+            for (int64_t e = g.begin(i); e < g.end(i); ++e) {
+                int j;
+                float wt;
+                g.edge(e, j, wt);
+                rs += (double)wt;
+            }
             const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
             part += 0.25 * ((double)ci * A + (double)si * B - rs);
             if (a.thetaT) a.thetaT[(size_t)x.r * a.n_total + x.off + i] = theta_from_phase(u[k][j]);
@@ -281,10 +363,13 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
     }
 }
 
-template <int QM>
+template <int QM, int MODE>
 __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
-    __shared__ float4 tab[2][kAdjMaxN];
+    extern __shared__ __align__(16) unsigned char smem[];
     const Ctx x = make_ctx(a);
+    const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
+    float4* const tabs = reinterpret_cast<float4*>(smem);
+    auto tab = [&](int k) { return tabs + (size_t)k * a.tabN; };
     const int q = QM ? QM : a.q;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwg = a.R * a.I;
@@ -298,12 +383,12 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
         const bool last = sg == a.nseg - 1;
         // recompute the segment's states from its checkpoint
         load_words(a, x, a.ckpt, sg, u);
-        put_sc(x, tab[p], u);
+        put_sc(x, tab(p), u);
         __syncthreads();
         for (int s = t0; s < t1; ++s) {
             store_words(a, x, a.seg, s - t0, u);
             if (s + 1 < t1 || last) {
-                fwd_step<QM>(a, x, s, tab[p], tab[p ^ 1], u);
+                fwd_step<QM>(a, x, g, s, tab(p), tab(p ^ 1), u);
                 p ^= 1;
                 __syncthreads();
             }
@@ -319,7 +404,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
                     lam[k][j] = 0.f;
                     if (m >= x.nq || i >= x.nb) continue;
                     float A, B, Cl, Dl;
-                    gather<false>(a, x, tab[p], i, A, B, Cl, Dl);
+                    gather<false>(g, tab(p), i, A, B, Cl, Dl);
                     const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
                     lam[k][j] = -0.5f * (si * A - ci * B);
                 }
@@ -337,7 +422,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
-                    tab[p][4 * m + j] = make_float4(si, ci, si * lam[k][j], ci * lam[k][j]);
+                    tab(p)[4 * m + j] = make_float4(si, ci, si * lam[k][j], ci * lam[k][j]);
                 }
             }
             __syncthreads();
@@ -354,7 +439,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
                     const int i = 4 * m + j;
                     if (i >= x.nb) break;
                     float A, B, Cl, Dl;
-                    gather<true>(a, x, tab[p], i, A, B, Cl, Dl);
+                    gather<true>(g, tab(p), i, A, B, Cl, Dl);
                     const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
                     const float l = lam[k][j];
                     const float csin = si * A - ci * B;
@@ -396,6 +481,61 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float4* gpart
 
 using AdjFn = void (*)(AdjArgs);
 
+// LDS bytes of the two tables, and of the CSR copy in each mode.
+size_t tab_bytes(int tabN) { return (size_t)32 * tabN; }
+size_t csr_bytes(int tabN, int64_t nnz, bool weights) {
+    size_t b = ((size_t)4 * (tabN + 1) + 15) & ~(size_t)15;
+    b += ((size_t)2 * nnz + 15) & ~(size_t)15;
+    if (weights) b += (size_t)4 * nnz;
+    return b;
+}
+constexpr size_t kAdjLdsLimit = 160 * 1024 - 256;  // dynamic LDS next to the static reduction slots
+
+// CSR placement for a problem: in LDS when it fits (unit weights need no
+// weight array), else read from global memory.
+int csr_mode(const Problem* p, int tabN, size_t* lds) {
+    const size_t t = tab_bytes(tabN);
+    const bool small_idx = p->max_inst_n <= 0x7fff;
+    if (small_idx && p->unit_weights && t + csr_bytes(tabN, p->max_inst_nnz, false) <= kAdjLdsLimit) {
+        *lds = t + csr_bytes(tabN, p->max_inst_nnz, false);
+        return kCsrLdsUnit;
+    }
+    if (small_idx && t + csr_bytes(tabN, p->max_inst_nnz, true) <= kAdjLdsLimit) {
+        *lds = t + csr_bytes(tabN, p->max_inst_nnz, true);
+        return kCsrLds;
+    }
+    *lds = t;
+    return kCsrGlobal;
+}
+
+AdjFn forward_fn(int q, int mode) {
+    const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
+    static const AdjFn f[3][3] = {
+        {adjoint_forward_kernel<0, 0>, adjoint_forward_kernel<0, 1>, adjoint_forward_kernel<0, 2>},
+        {adjoint_forward_kernel<2, 0>, adjoint_forward_kernel<2, 1>, adjoint_forward_kernel<2, 2>},
+        {adjoint_forward_kernel<3, 0>, adjoint_forward_kernel<3, 1>, adjoint_forward_kernel<3, 2>}};
+    return f[qc][mode];
+}
+
+AdjFn backward_fn(int q, int mode) {
+    const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
+    static const AdjFn f[3][3] = {
+        {adjoint_backward_kernel<0, 0>, adjoint_backward_kernel<0, 1>, adjoint_backward_kernel<0, 2>},
+        {adjoint_backward_kernel<2, 0>, adjoint_backward_kernel<2, 1>, adjoint_backward_kernel<2, 2>},
+        {adjoint_backward_kernel<3, 0>, adjoint_backward_kernel<3, 1>, adjoint_backward_kernel<3, 2>}};
+    return f[qc][mode];
+}
+
+int launch_adj(AdjFn fn, size_t lds, int grid, hipStream_t stream, const AdjArgs& a,
+               const char* what) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return hip_error(e, what);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(kAdjTB), lds, stream, a);
+    e = hipGetLastError();
+    return e == hipSuccess ? OIM_OK : hip_error(e, what);
+}
+
 int check_launch(const char* what) {
     const hipError_t e = hipGetLastError();
     return e == hipSuccess ? OIM_OK : hip_error(e, what);
@@ -418,6 +558,8 @@ AdjArgs base_args(const Problem* p, const oim_adjoint_cfg* cfg, const float* K, 
     a.nseg = (cfg->steps + cfg->checkpoint_every - 1) / cfg->checkpoint_every;
     a.step0 = step0;
     a.dt = cfg->dt;
+    a.tabN = (p->max_inst_n + 3) & ~3;
+    a.max_nnz = p->max_inst_nnz;
     a.K = K;
     a.Ks = Ks;
     a.sigma = sigma;
@@ -441,10 +583,10 @@ int launch_adjoint_forward(Problem* p, const oim_adjoint_cfg* cfg, const float* 
     a.ckpt = ckpt;
     a.thetaT = thetaT;
     a.loss = loss;
-    AdjFn fn = cfg->q == 2 ? adjoint_forward_kernel<2> : cfg->q == 3 ? adjoint_forward_kernel<3>
-                                                                       : adjoint_forward_kernel<0>;
-    hipLaunchKernelGGL(fn, dim3(cfg->R * p->n_inst), dim3(kAdjTB), 0, stream, a);
-    return check_launch("adjoint_forward_kernel");
+    size_t lds = 0;
+    const int mode = csr_mode(p, a.tabN, &lds);
+    return launch_adj(forward_fn(cfg->q, mode), lds, cfg->R * p->n_inst, stream, a,
+                      "adjoint_forward_kernel");
 }
 
 int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
@@ -474,10 +616,9 @@ int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float*
     a.ckpt = const_cast<uint32_t*>(ckpt);
     a.seg = reinterpret_cast<uint32_t*>(w);
     a.gpart = reinterpret_cast<float4*>(w + (seg_bytes + 255) / 256 * 256);
-    AdjFn fn = cfg->q == 2 ? adjoint_backward_kernel<2> : cfg->q == 3 ? adjoint_backward_kernel<3>
-                                                                        : adjoint_backward_kernel<0>;
-    hipLaunchKernelGGL(fn, dim3(nwg), dim3(kAdjTB), 0, stream, a);
-    int st = check_launch("adjoint_backward_kernel");
+    size_t lds = 0;
+    const int mode = csr_mode(p, a.tabN, &lds);
+    int st = launch_adj(backward_fn(cfg->q, mode), lds, nwg, stream, a, "adjoint_backward_kernel");
     if (st) return st;
     hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((cfg->steps + 255) / 256), dim3(256), 0, stream,
                        a.gpart, cfg->steps, nwg * kAdjWaves, gK, gKs, gS);

@@ -123,11 +123,19 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     p->nnz = nnz;
     p->n_inst = n_inst;
     p->max_inst_n = n;
+    p->max_inst_nnz = nnz;
     if (n_inst > 1) {
         p->max_inst_n = 0;
-        for (int32_t b = 0; b < n_inst; ++b)
+        p->max_inst_nnz = 0;
+        for (int32_t b = 0; b < n_inst; ++b) {
             p->max_inst_n = std::max(p->max_inst_n, inst_off[b + 1] - inst_off[b]);
+            p->max_inst_nnz = std::max<int64_t>(p->max_inst_nnz,
+                                                row_ptr[inst_off[b + 1]] - row_ptr[inst_off[b]]);
+        }
     }
+    p->unit_weights = true;
+    for (int64_t e = 0; e < nnz && p->unit_weights; ++e)
+        if (std::fabs(J[e]) != 1.0f) p->unit_weights = false;
     weight_stats(p, n, row_ptr, col_idx, J);
     SellImage img;
     build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img);

@@ -56,6 +56,8 @@ struct Problem {
     // instances of a block-diagonal batch (1 for a single graph)
     int32_t n_inst = 1;
     int32_t max_inst_n = 0;  // largest instance (oscillators)
+    int64_t max_inst_nnz = 0;  // most stored entries of one instance
+    bool unit_weights = false; // every |J| is 1
     int4* d_inst = nullptr;
     int32_t* d_order = nullptr;
     int32_t max_slices = 0;

@@ -254,3 +254,25 @@ def test_adjoint_full_batch_prefix_matches_oracle(oim, orc, dev):
         ok, rel = _close_vec(got, ref, 1e-4)
         print(f"full batch d/d{name}: max rel err {rel:.2e}")
         assert ok, (name, rel)
+
+
+def test_adjoint_rows_from_global_memory_match_oracle(oim, orc, dev):
+    # an instance whose rows do not fit in LDS next to the tables (about
+    # 90 000 stored entries) is gathered from global memory instead
+    g = synth.gnp_avg_degree(1500, 60.0, seed=6)
+    J = -g.w
+    steps, R, C = 25, 1, 10
+    K, Ks, sg = _schedules(steps)
+    K = (K / 20.0).astype(np.float32)  # keep dt * K * degree small
+    th0 = synth.theta0(R, g.n, seed=2)
+    sd = synth.seeds(R, 1)
+    with oim.Problem.from_csr(g.n, g.row_ptr, g.col, J.astype(np.float32)) as prob:
+        loss, thT, gK, gKs, gS = _gpu_adjoint(oim, prob, th0, K, Ks, sg, sd, 2, C)
+    L, oK, oKs, oS = orc.adjoint_csr(g.row_ptr, g.col, J.astype(np.float64),
+                                     th0.astype(np.float64), q=2, dt=DT, K=K, Ks=Ks, sigma=sg,
+                                     seeds=sd)
+    assert loss.sum() == pytest.approx(L, rel=1e-5)
+    for got, ref, name in ((gK, oK, "K"), (gKs, oKs, "Ks"), (gS, oS, "sigma")):
+        ok, rel = _close_vec(got, ref, 1e-4)
+        print(f"global rows d/d{name}: max rel err {rel:.2e}")
+        assert ok, (name, rel)
