@@ -137,6 +137,9 @@ int oim_problem_info_get(oim_problem p, oim_problem_info* info);
 #define OIM_PREC_FP32        0x0u  /* FP32 coupling sum                              */
 #define OIM_PREC_BF16X3      0x10u /* dense only: BF16 three-term split on MFMA       */
 #define OIM_PREC_MASK        0x30u
+#define OIM_SCHED_PER_REPLICA 0x100u /* K, Ks, sigma are [R][steps]: one schedule per  */
+                                     /* replica (shared by its instances); default     */
+                                     /* [steps] for every replica                      */
 
 typedef struct {
     int32_t q;              /* stable phases per oscillator: 2 = Ising, 3.. = Potts (<= 16) */
@@ -145,7 +148,7 @@ typedef struct {
     float dt;               /* time step h of Algorithm 1, finite and > 0                  */
     int32_t readout_every;  /* M > 0: threshold + energy every M steps and after the last  */
                             /* step; 0: no in-run readout                                  */
-    uint32_t flags;         /* OIM_LOOP_* | OIM_PREC_*                                      */
+    uint32_t flags;         /* OIM_LOOP_* | OIM_PREC_* | OIM_SCHED_PER_REPLICA               */
 } oim_run_cfg;
 
 /* Optional in-run readout buffers (device memory, any may be NULL).
@@ -166,7 +169,9 @@ typedef struct {
 } oim_readout;
 
 /* K, Ks, sigma: device FP32 [steps], indexed by the LOCAL step s = 0..steps-1
- * (coupling strength, SHIL strength, noise amplitude per step).
+ * (coupling strength, SHIL strength, noise amplitude per step); with
+ * OIM_SCHED_PER_REPLICA they are [R][steps], row r driving replica r (a
+ * batched sweep of annealing schedules, as in Sec. III-D / Fig. 3b).
  * seeds: device uint64 [R].  step0: global index of the first step (noise
  * counter).  theta: device FP32 [R][n], overwritten with the final phases in
  * [0, 2pi).  phase: NULL, or device uint32 [R][n] phase words; when given,

@@ -109,8 +109,24 @@ def _sched(a, steps):
     return a
 
 
+def _per_replica(fn, theta0, K, Ks, sigma, seeds, **kw):
+    """Schedules given per replica ([R][steps]): replicas are independent, so
+    each one is integrated on its own with its own row of the schedules."""
+    th = np.atleast_2d(np.asarray(theta0, np.float64))
+    sd = np.asarray(seeds, np.uint64)
+    out = np.empty_like(th)
+    for r in range(th.shape[0]):
+        out[r] = fn(th[r:r + 1], K=np.asarray(K)[r], Ks=np.asarray(Ks)[r],
+                    sigma=np.asarray(sigma)[r], seeds=sd[r:r + 1], **kw)[0]
+    return out
+
+
 def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
-    """Integrate Eq. 5 (Algorithm 1) on a CSR coupling; returns theta [R][n] in FP64."""
+    """Integrate Eq. 5 (Algorithm 1) on a CSR coupling; returns theta [R][n] in FP64.
+    K, Ks, sigma are [steps] (shared) or [R][steps] (one schedule per replica)."""
+    if np.ndim(K) == 2:
+        return _per_replica(lambda th, **k: run_csr(row_ptr, col, J, th, **k), theta0, K, Ks,
+                            sigma, seeds, q=q, dt=dt, step0=step0, nthreads=nthreads)
     rp = _c(row_ptr, np.int64)
     cl = _c(col, np.int32)
     Jv = _c(J, np.float64)
@@ -132,6 +148,10 @@ def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nth
 def run_csr_blocks(row_ptr, col, J, inst_off, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0,
                    nthreads=0):
     """Integrate a block-diagonal batch of instances (inst_off[b]..inst_off[b+1]-1)."""
+    if np.ndim(K) == 2:
+        return _per_replica(lambda th, **k: run_csr_blocks(row_ptr, col, J, inst_off, th, **k),
+                            theta0, K, Ks, sigma, seeds, q=q, dt=dt, step0=step0,
+                            nthreads=nthreads)
     rp = _c(row_ptr, np.int64)
     cl = _c(col, np.int32)
     Jv = _c(J, np.float64)
@@ -192,6 +212,9 @@ def relaxed_cut(row_ptr, col, J, theta):
 
 def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
     """Integrate Eq. 5 with the all-pairs (dense) coupling sum, diagonal ignored."""
+    if np.ndim(K) == 2:
+        return _per_replica(lambda th, **k: run_dense(J, th, **k), theta0, K, Ks, sigma, seeds,
+                            q=q, dt=dt, step0=step0, nthreads=nthreads)
     Jd = _c(J, np.float64)
     th = np.array(theta0, dtype=np.float64, order="C", copy=True)
     if th.ndim == 1:

@@ -20,11 +20,11 @@ import torch
 
 from . import _lib
 from ._lib import (OIM_LOOP_AUTO, OIM_LOOP_PERSISTENT, OIM_LOOP_STEPWISE, OIM_PREC_BF16X3,
-                   OIM_PREC_FP32, AdjointCfg, OimError, Readout, RunCfg, check, lib)
+                   OIM_PREC_FP32, OIM_SCHED_PER_REPLICA, AdjointCfg, OimError, Readout, RunCfg, check, lib)
 
 __all__ = [
     "OIM_LOOP_AUTO", "OIM_LOOP_PERSISTENT", "OIM_LOOP_STEPWISE", "OIM_PREC_FP32",
-    "OIM_PREC_BF16X3", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
+    "OIM_PREC_BF16X3", "OIM_SCHED_PER_REPLICA", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
     "oim_problem_from_csr_blocks", "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
     "oim_round", "oim_cut", "oim_conflicts", "oim_energy", "oim_phase_from_theta",
     "oim_theta_from_phase", "oim_autotune", "oim_set_tuning",
@@ -133,7 +133,11 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
     if theta.dim() != 2 or theta.shape[1] != n:
         raise ValueError("theta must be [R][n]")
     R = int(theta.shape[0])
-    steps = int(K.shape[0])
+    per_replica = K.dim() == 2
+    steps = int(K.shape[-1])
+    if per_replica:
+        flags = int(flags) | OIM_SCHED_PER_REPLICA
+    sshape = (R, steps) if per_replica else (steps,)
     cfg = RunCfg(int(q), R, steps, float(dt), int(readout_every), int(flags))
     nr = n_readouts(steps, readout_every)
     RI = R * int(oim_problem_info_get(h)["n_instances"])
@@ -141,9 +145,9 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
                  _dev(best_h, torch.float64, (RI,), "best_h", True),
                  _dev(best_step, torch.int32, (RI,), "best_step", True),
                  _dev(best_colour, torch.int8, (R, n), "best_colour", True))
-    check(lib().oim_run(h, ctypes.byref(cfg), _dev(K, torch.float32, (steps,), "K"),
-                        _dev(Ks, torch.float32, (steps,), "Ks"),
-                        _dev(sigma, torch.float32, (steps,), "sigma"),
+    check(lib().oim_run(h, ctypes.byref(cfg), _dev(K, torch.float32, sshape, "K"),
+                        _dev(Ks, torch.float32, sshape, "Ks"),
+                        _dev(sigma, torch.float32, sshape, "sigma"),
                         _dev(seeds, torch.uint64, (R,), "seeds"), int(step0),
                         _dev(theta, torch.float32, None, "theta"),
                         _dev(phase, torch.uint32, (R, n), "phase", True), ctypes.byref(ro),
@@ -328,7 +332,7 @@ def run(problem: Problem, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0,
         step0=0, want_best=False, phase=None, stream=None):
     """oim_run on a Problem; returns the readout tensors when readout_every > 0."""
     R, n = theta.shape
-    steps = int(K.shape[0])
+    steps = int(K.shape[-1])
     out = {}
     if readout_every > 0:
         dev = theta.device

@@ -13,6 +13,7 @@ OIM_E_UNSUPPORTED, OIM_E_NOMEM, OIM_E_HIP, OIM_E_STATE = 5, 6, 7, 8
 
 OIM_LOOP_AUTO, OIM_LOOP_PERSISTENT, OIM_LOOP_STEPWISE = 0x0, 0x1, 0x2
 OIM_PREC_FP32, OIM_PREC_BF16X3 = 0x0, 0x10
+OIM_SCHED_PER_REPLICA = 0x100
 
 _P = ctypes.c_void_p
 _i32, _i64, _u32, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float

@@ -79,10 +79,10 @@ struct DenseArgs {
     uint32_t* U;           // [Rp][np] phase words
     const uint64_t* seeds;
     int np, Rp, n, R, q, nk;
-    float kc, ks, ns;      // step coefficients in 2^-32-turn units (unused for init)
-    const float* K;
+    const float* K;        // schedules, [steps] or [R][steps] (sched_stride = steps)
     const float* Ks;
     const float* sigma;
+    int sched_stride;
     int s;                 // local step index
     uint32_t t;            // global step index
     float dt, sqrt_dt;
@@ -241,10 +241,15 @@ void dense_step_kernel(DenseArgs a) {
     const int qi0 = i0 + wm * 64 + 4 * (lane >> 4);  // first row of the quads of block b = 0
     uint4 uq[2][4];
     uint64_t seedv[2];
+    float sK[2], sKs[2], sS[2];
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
         seedv[cb] = r < a.R ? a.seeds[r] : 0ull;
+        const int64_t so = (int64_t)(r < a.R ? r : 0) * a.sched_stride + a.s;
+        sK[cb] = a.K[so];
+        sKs[cb] = a.Ks[so];
+        sS[cb] = a.sigma[so];
 #pragma unroll
         for (int b = 0; b < 4; ++b)
             uq[cb][b] = *reinterpret_cast<const uint4*>(a.U + (size_t)r * np + qi0 + b * 16);
@@ -254,11 +259,14 @@ void dense_step_kernel(DenseArgs a) {
     __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
 
     // ---- epilogue: SHIL, noise, Euler-Maruyama update, next split X ----
-    const float kcoef = a.kc, kscoef = a.ks, nscoef = a.ns;
 #pragma unroll
     for (int cb = 0; cb < 2; ++cb) {
         const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
         const bool rvalid = r < a.R;
+        // step coefficients in 2^-32-turn units
+        const float kcoef = -a.dt * sK[cb] * kTurnScale;
+        const float kscoef = -a.dt * sKs[cb] * kTurnScale;
+        const float nscoef = sS[cb] * a.sqrt_dt * kTurnScale;
         const uint32_t k0 = (uint32_t)seedv[cb], k1 = (uint32_t)(seedv[cb] >> 32);
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
@@ -491,25 +499,20 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     a.n = n;
     a.R = R;
     a.q = cfg->q;
-    // schedule values are read on the host side of each launch from device
-    // memory only through the coefficients below; copy the schedule once.
-    std::vector<float> hK(cfg->steps), hKs(cfg->steps), hS(cfg->steps);
-    hipError_t e = hipMemcpyAsync(hK.data(), K, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hKs.data(), Ks, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(hS.data(), sigma, sizeof(float) * cfg->steps, hipMemcpyDeviceToHost, stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_error(e, "copy schedules");
-    const float dt = cfg->dt;
-    const float sqrt_dt = std::sqrt(dt);
-    const float scale = 683565275.57643158978045f;
+    // the step kernels read their schedule entries from device memory
+    a.K = K;
+    a.Ks = Ks;
+    a.sigma = sigma;
+    a.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
+    a.dt = cfg->dt;
+    a.sqrt_dt = std::sqrt(cfg->dt);
+    hipError_t e = hipSuccess;
     dim3 grid(np / kTM, Rp / kTR);
     for (int s = 0; s < cfg->steps; ++s) {
         a.Xin = (s & 1) ? X1 : X0;
         a.Xout = (s & 1) ? X0 : X1;
         a.t = (uint32_t)(step0 + s);
-        a.kc = -dt * hK[s] * scale;
-        a.ks = -dt * hKs[s] * scale;
-        a.ns = hS[s] * sqrt_dt * scale;
+        a.s = s;
         hipLaunchKernelGGL(fn, grid, dim3(kTB), 0, stream, a);
         if ((st = check_launch("dense_step_kernel"))) return st;
         if (M > 0 && ((s + 1) % M == 0 || s + 1 == cfg->steps)) {

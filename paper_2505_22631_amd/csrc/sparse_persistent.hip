@@ -56,6 +56,7 @@ struct PersistArgs {
     int32_t* best_step; // [R][I]
     int8_t* best_colour;  // [R][n_total]
     int32_t R;
+    int32_t sched_stride;  // 0: one schedule for all replicas; steps: [R][steps]
 };
 
 __device__ __forceinline__ int4 load_pair(__amdgpu_buffer_rsrc_t rsrc, int voff, int soff) {
@@ -124,9 +125,10 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     // chunk's vector loads in flight while the current chunk is used; each
     // step reads its three values with v_readlane, so no step waits on a
     // scalar load.
+    const int64_t sched_off = (int64_t)r * a.sched_stride;
     auto sched = [&](const float* v, int c) {
         const int i = c * 64 + lane;
-        return i < a.steps ? v[i] : 0.0f;
+        return i < a.steps ? v[sched_off + i] : 0.0f;
     };
     float cK = sched(a.K, 0), cKs = sched(a.Ks, 0), cS = sched(a.sigma, 0);
     float nK = sched(a.K, 1), nKs = sched(a.Ks, 1), nS = sched(a.sigma, 1);
@@ -441,6 +443,7 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
     a.best_step = ro ? ro->best_step : nullptr;
     a.best_colour = ro ? ro->best_colour : nullptr;
     a.R = cfg->R;
+    a.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
     const int qi = cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0;
     KernelFn fn = v->fn[qi];
     const size_t lds = lds_bytes(plane, v->tb);

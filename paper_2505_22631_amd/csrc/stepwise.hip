@@ -47,6 +47,7 @@ struct StepArgs {
     int steps, n, R, Rp, q;
     int64_t step0;
     float dt;
+    int sched_stride;     // 0: one schedule for all replicas; steps: [R][steps]
 };
 
 template <int QM>
@@ -60,9 +61,10 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int Rp = a.Rp, q = QM ? QM : a.q;
     const uint32_t t = (uint32_t)(a.step0 + s);
     const float sqrt_dt = __builtin_sqrtf(a.dt);
-    const float kc = -a.dt * a.K[s] * kTurnScale;
-    const float ks = -a.dt * a.Ks[s] * kTurnScale;
-    const float ns = a.sigma[s] * sqrt_dt * kTurnScale;
+    const int64_t so = (int64_t)(r < a.R ? r : 0) * a.sched_stride + s;
+    const float kc = -a.dt * a.K[so] * kTurnScale;
+    const float ks = -a.dt * a.Ks[so] * kTurnScale;
+    const float ns = a.sigma[so] * sqrt_dt * kTurnScale;
     const uint64_t seed = r < a.R ? a.seeds[r] : 0ull;
     float z[4];
     normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
@@ -296,6 +298,7 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     sa.q = cfg->q;
     sa.step0 = step0;
     sa.dt = cfg->dt;
+    sa.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
     ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, base, 0, steps, n, Rp, cfg->q};
     BestArgs ba{};
     ba.part = part;

@@ -106,7 +106,7 @@ int validate_cfg(const Problem* p, const oim_run_cfg* cfg) {
     if (!(cfg->dt > 0.0f) || !std::isfinite(cfg->dt))
         return set_error(OIM_E_ARG, "dt must be finite and > 0");
     if (cfg->readout_every < 0) return set_error(OIM_E_ARG, "readout_every must be >= 0");
-    const uint32_t known = OIM_LOOP_MASK | OIM_PREC_MASK;
+    const uint32_t known = OIM_LOOP_MASK | OIM_PREC_MASK | OIM_SCHED_PER_REPLICA;
     if (cfg->flags & ~known) return set_error(OIM_E_ARG, "unknown flag bits");
     const uint32_t loop = cfg->flags & OIM_LOOP_MASK;
     const uint32_t prec = cfg->flags & OIM_PREC_MASK;
