@@ -414,6 +414,85 @@ def bench_adjoint(args):
     prob.close()
 
 
+def bench_sweep(args):
+    """Batched annealing-schedule sweep (the kind of study of Sec. III-D /
+    Fig. 3b) on the 100x100 +-1 torus: an 8 x 8 grid of (K_max, Ks_max)
+    multipliers, 4 replicas per cell, every replica with its own ramp of K and
+    triangular Ks, all 256 replicas in one launch, against one launch per
+    cell."""
+    import torch
+    import paper_2505_22631_amd as oim
+    import synth
+    g = synth.torus(100, 100, seed=1, signed=True)
+    steps, q, M, per_cell = 10000, 2, 100, 4
+    kg = [0.25, 0.5, 1.0, 1.5, 2.0, 3.0, 4.0, 6.0]
+    ksg = [0.125, 0.25, 0.5, 0.75, 1.0, 1.5, 2.0, 3.0]
+    dt = float(np.float32(0.01))
+    dev = torch.device("cuda:0")
+    prob = oim.Problem.from_csr(g.n, g.row_ptr, g.col, (-g.w).astype(np.float32))
+    rowsum = prob.info["max_abs_row_sum"]
+    cells = [(a, b) for a in kg for b in ksg]
+    R = len(cells) * per_cell
+    K = np.stack([synth.ramp(0.0, a * 0.5 / (dt * rowsum), steps) for a, b in cells
+                  for _ in range(per_cell)]).astype(np.float32)
+    Ks = np.stack([synth.triangle(b * 0.5 / (dt * q), 5, steps) for a, b in cells
+                   for _ in range(per_cell)]).astype(np.float32)
+    sg = np.full((R, steps), 0.1, np.float32)
+    dK, dKs, dsg = (torch.from_numpy(x).to(dev) for x in (K, Ks, sg))
+    th_init = torch.from_numpy(synth.theta0(R, g.n, seed=100)).to(dev)
+    seeds = torch.from_numpy(synth.seeds(R, 0)).to(dev)
+    theta = torch.empty_like(th_init)
+    best_h = torch.empty(R, dtype=torch.float64, device=dev)
+    trace = torch.empty((oim.n_readouts(steps, M), R), dtype=torch.float64, device=dev)
+    best_step = torch.empty(R, dtype=torch.int32, device=dev)
+    from paper_2505_22631_amd import tune
+    launch, _ = tune.tuned(prob, th_init, dK[0], dKs[0], dsg[0], seeds, q=q, dt=dt,
+                           trial_steps=500)
+
+    def sweep():
+        theta.copy_(th_init)
+        oim.oim_run(prob.handle, g.n, theta, dK, dKs, dsg, seeds, q=q, dt=dt, readout_every=M,
+                    trace=trace, best_h=best_h, best_step=best_step)
+
+    for _ in range(args.warmup):
+        sweep()
+    t_batched = float(np.median([_sync_time(sweep) for _ in range(args.steps)]))
+    W = -prob.info["sum_J_upper"]
+    cut = (W - best_h.cpu().numpy()) / 2.0
+    grid = cut.reshape(len(kg), len(ksg), per_cell).max(axis=2)
+    # plain: one launch per cell (its 4 replicas), the first 8 cells timed
+    per = []
+    for c in range(min(8, len(cells))):
+        sl = slice(c * per_cell, (c + 1) * per_cell)
+        thc = th_init[sl].clone()
+
+        def one():
+            thc.copy_(th_init[sl])
+            oim.oim_run(prob.handle, g.n, thc, dK[sl].contiguous(), dKs[sl].contiguous(),
+                        dsg[sl].contiguous(), seeds[sl].contiguous(), q=q, dt=dt)
+        one()
+        per.append(_sync_time(one))
+    plain_total = float(np.mean(per)) * len(cells)
+    eu = float(g.nnz) * R * steps
+    bi, bj = np.unravel_index(np.argmax(grid), grid.shape)
+    out = {
+        "metric": "edge-updates/s & time-to-99%-best-cut, batched vs plain, 1 MI355X",
+        "value": eu / t_batched, "unit": "edge-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_batched * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "schedule sweep on the 100x100 +-1 torus: 8 x 8 (K_max, Ks_max) "
+                               "grid x 4 replicas, per-replica schedules, one launch",
+                   "replicas": R, "em_steps": steps, "K_multipliers": kg, "Ks_multipliers": ksg},
+        "launch": {"block": launch["block"], "slices_per_wave": launch["slices_per_wave"]},
+        "best_cut_grid": grid.tolist(),
+        "best_cell": {"K_mult": kg[bi], "Ks_mult": ksg[bj], "cut": float(grid[bi, bj])},
+        "plain": {"ms_per_cell": float(np.mean(per)) * 1e3, "ms_total_extrapolated":
+                  plain_total * 1e3, "speedup_batched": plain_total / t_batched},
+    }
+    print(json.dumps(out))
+    prob.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -441,6 +520,8 @@ def main():
         return bench_colouring(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import torch
     import paper_2505_22631_amd as oim
