@@ -63,8 +63,13 @@ __device__ __forceinline__ int4 load_pair(__amdgpu_buffer_rsrc_t rsrc, int voff,
     return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0));
 }
 
-__device__ __forceinline__ float2 sc_at(const unsigned char* smem, int byte_off) {
-    return *reinterpret_cast<const float2*>(smem + byte_off);
+// (sin, cos) of the oscillator at an LDS byte offset.  The dynamic LDS of
+// this kernel is its only LDS and starts at address 0, so the offset is the
+// address itself (no per-edge base add).
+__device__ __forceinline__ float2 sc_at(const unsigned char*, int byte_off) {
+    typedef __attribute__((address_space(3))) const uint64_t lds_u64;
+    const uint64_t v = *reinterpret_cast<lds_u64*>((uint32_t)byte_off);
+    return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
 template <int TB, int MS, int QM>
@@ -168,16 +173,24 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                         v[j][0] = load_pair(rsrc, voff, soff);
                         v[j][1] = load_pair(rsrc, voff + 1024, soff);
                     }
+                    // all 16 neighbour reads of the iteration are in flight
+                    // before the first multiply-add consumes one
+                    float2 p[2][4][2];
+#pragma unroll
+                    for (int h = 0; h < 2; ++h)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            p[h][j][0] = sc_at(smem, v[j][h].x);
+                            p[h][j][1] = sc_at(smem, v[j][h].z);
+                        }
 #pragma unroll
                     for (int h = 0; h < 2; ++h) {
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
-                            const float2 p0 = sc_at(smem, v[j][h].x);
-                            const float2 p1 = sc_at(smem, v[j][h].z);
-                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p0.y, A[j]);
-                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p0.x, B[j]);
-                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p1.y, A[j]);
-                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p1.x, B[j]);
+                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p[h][j][0].y, A[j]);
+                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p[h][j][0].x, B[j]);
+                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p[h][j][1].y, A[j]);
+                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p[h][j][1].x, B[j]);
                         }
                     }
                 }
