@@ -6,10 +6,11 @@
 //   phase A  every oscillator's coupling sum from the phases of step t,
 //            c_i = sum_j J_ij sin(th_i - th_j) = s_i sum_j J_ij c_j - c_i sum_j J_ij s_j,
 //            gathered over the sliced-ELL rows from the (sin, cos) table in LDS,
-//            folded with the SHIL term into drift_i (registers)
+//            folded with the SHIL term and the Philox noise into the step's
+//            increment drift_i (registers)
 //   barrier
-//   phase B  Philox noise, Euler-Maruyama update, wrap, and the (sin, cos)
-//            table refreshed for step t+1
+//   phase B  Euler-Maruyama update, wrap, and the (sin, cos) table refreshed
+//            for step t+1
 //   barrier
 // The state is a 32-bit fixed-point phase per oscillator (phase.hpp), held
 // in registers; the step in 2^-32-turn units is
@@ -157,22 +158,43 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         const float ks = -a.dt * Kst * kTurnScale;
         const float ns = St * sqrt_dt * kTurnScale;
 
-        // ---- phase A: coupling sums over the sliced-ELL rows ----
-        // 4 edges of each of the slice's 4 rows per iteration: 8 16-byte
-        // buffer loads (scalar offsets, no per-lane address math), 16 LDS reads.
+        // ---- phase A: noise, and coupling sums over the sliced-ELL rows ----
+        // The first edge loads of a slice are issued, then its Philox noise
+        // is computed while they are in flight (the noise depends only on
+        // the replica, the quad and the step); 4 edges of each of the slice's
+        // 4 rows per iteration: 8 16-byte buffer loads (scalar offsets, no
+        // per-lane address math), 16 LDS reads.  drift then holds the whole
+        // increment of the step, noise included.
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
             if (wave + k * W < S) {
+                const int m = (wave + k * W) * 64 + lane;
                 const int D2 = sdeg[k] >> 1;
-                float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
-                for (int e2 = 0; e2 < D2; e2 += 2) {
-                    int4 v[4][2];
+                int4 v[4][2];
+                auto load_iter = [&](int e2) __attribute__((always_inline)) {
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int soff = (sbase[k] + j * D2 + e2) * 1024;
                         v[j][0] = load_pair(rsrc, voff, soff);
                         v[j][1] = load_pair(rsrc, voff + 1024, soff);
                     }
+                };
+                if (D2 > 0) load_iter(0);
+                // The quad index and the key are re-materialised every step
+                // (empty asm) so partial Philox rounds are not precomputed
+                // and kept live in registers across the whole run.
+                uint32_t mm = (uint32_t)m, kk0 = k0, kk1 = k1;
+                asm volatile("" : "+v"(mm), "+s"(kk0), "+s"(kk1));
+                // the normals wait in drift, whose registers are free until
+                // the sums below are complete; the empty asm keeps their
+                // computation here, in the shadow of the loads, instead of
+                // letting it sink to its use after the sums
+                normals4(mm, t, (uint32_t)inst_id, kk0, kk1, drift[k]);
+                asm volatile("" : "+v"(drift[k][0]), "+v"(drift[k][1]), "+v"(drift[k][2]),
+                             "+v"(drift[k][3]));
+                float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
+                for (int e2 = 0; e2 < D2; e2 += 2) {
+                    if (e2 > 0) load_iter(e2);
                     // all 16 neighbour reads of the iteration are in flight
                     // before the first multiply-add consumes one
                     float2 p[2][4][2];
@@ -194,18 +216,18 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                         }
                     }
                 }
-                const int m = (wave + k * W) * 64 + lane;
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float2 own = sc[j * plane + m];
                     const float coup = own.x * A[j] - own.y * B[j];
-                    drift[k][j] = kc * coup + ks * sin_q<QM>(own.x, own.y, ph[k][j], q);
+                    const float det = kc * coup + ks * sin_q<QM>(own.x, own.y, ph[k][j], q);
+                    drift[k][j] = __builtin_fmaf(ns, drift[k][j], det);
                 }
             }
         }
         __syncthreads();
 
-        // ---- phase B: noise, Euler-Maruyama update, wrap, table refresh ----
+        // ---- phase B: Euler-Maruyama update, wrap, table refresh ----
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
             const int slice = wave + k * W;
@@ -214,16 +236,9 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             // others (their slots exist in every plane) but no edge reads them,
             // which keeps per-lane masks out of the loop.
             if (slice < S) {
-                // The quad index and the key are re-materialised every step
-                // (empty asm) so partial Philox rounds are not precomputed
-                // and kept live in registers across the whole run.
-                uint32_t mm = (uint32_t)m, kk0 = k0, kk1 = k1;
-                asm volatile("" : "+v"(mm), "+s"(kk0), "+s"(kk1));
-                float z[4];
-                normals4(mm, t, (uint32_t)inst_id, kk0, kk1, z);
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    const uint32_t u = advance(ph[k][j], __builtin_fmaf(ns, z[j], drift[k][j]));
+                    const uint32_t u = advance(ph[k][j], drift[k][j]);
                     ph[k][j] = u;
                     sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
                 }
