@@ -138,13 +138,15 @@ def cpu_baseline(wl, target_s=15.0):
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def bench_dense(args):
-    """Dense SK Ising: n = 4096, J_ij ~ N(0, 1/n) (seed 3), 512 replicas,
-    coupling as a BF16x3 GEMM on the matrix cores, 1000 steps."""
+def bench_dense(args, n=4096):
+    """Dense SK Ising: J_ij ~ N(0, 1/n) (seed 3), 512 replicas, coupling as a
+    BF16x3 GEMM on the matrix cores; n = 4096 (1000 steps) or the paper's
+    largest all-to-all size n = 20000 (100 steps)."""
     import torch
     import paper_2505_22631_amd as oim
     import synth
-    n, R, steps, q = 4096, 512, args.dense_steps, 2
+    R, q = 512, 2
+    steps = args.dense_steps or (1000 if n == 4096 else 100)
     dt = float(np.float32(0.01))
     J = synth.sk_dense(n, seed=3)
     dev = torch.device("cuda:0")
@@ -194,7 +196,7 @@ def bench_dense(args):
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
         "data": "synthetic",
-        "config": {"workload": "dense SK Ising n=4096, 512 replicas, BF16x3 MFMA coupling",
+        "config": {"workload": f"dense SK Ising n={n}, 512 replicas, BF16x3 MFMA coupling",
                    "n": n, "replicas": R, "em_steps": steps, "K_max": kmax, "Ks_max": ksmax},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
@@ -498,11 +500,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="torus")
+    ap.add_argument("--workload", default="torus",
+                    choices=["torus", "gnp800", "sk4096", "sk20000", "colouring", "adjoint", "sweep"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", type=int, default=8,
                     help="replicas to time in the plain one-launch-per-replica loop")
-    ap.add_argument("--dense-steps", type=int, default=1000)
+    ap.add_argument("--dense-steps", type=int, default=0,
+                    help="EM steps per dense solve (0: 1000 at n = 4096, 100 at n = 20000)")
     ap.add_argument("--plain-graphs", type=int, default=32,
                     help="graphs timed in the plain per-graph loop of the batched workloads")
     ap.add_argument("--ref-mult", type=int, default=10,
@@ -516,6 +520,8 @@ def main():
 
     if args.workload == "sk4096":
         return bench_dense(args)
+    if args.workload == "sk20000":
+        return bench_dense(args, n=20000)
     if args.workload == "colouring":
         return bench_colouring(args)
     if args.workload == "adjoint":

@@ -131,3 +131,34 @@ def test_dense_full_size_sampled_replicas(oim, orc):
           f"(split bound {bound:.2e})", flush=True)
     assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
     assert err < max(1e-5, 20 * bound)
+
+
+def test_dense_paper_scale_sampled_replica(oim, orc):
+    # the paper's largest all-to-all size, n = 20000 (J is 1.6 GB in FP32;
+    # 20000 is not a multiple of the 128-row tile, so the last row tile is
+    # ragged), 64 replicas; the last replica is checked against the oracle
+    # over 2 steps, the others must stay finite and in [0, 2pi)
+    n, R, steps = 20000, 64, 2
+    rng = np.random.default_rng(11)
+    J = (rng.standard_normal((n, n), dtype=np.float32) / np.float32(np.sqrt(n)))
+    J = np.triu(J, k=1)
+    J += J.T
+    with oim.Problem.from_dense(J) as prob:
+        kmax = 32.0 * 0.5 / (DT * prob.info["max_abs_row_sum"])
+        K = synth.ramp(0.0, kmax, 100)[50:50 + steps].copy()
+        Ks = synth.const(0.5, steps)
+        sg = synth.const(0.1, steps)
+        th0 = synth.theta0(R, n, seed=101)
+        sd = synth.seeds(R, 3)
+        got, _ = _run(oim, prob, th0, K, Ks, sg, sd, 2, step0=7)
+    pick = [R - 1]
+    Jd = J.astype(np.float64)
+    del J
+    want = orc.run_dense(Jd, th0[pick], q=2, dt=DT, K=K, Ks=Ks, sigma=sg, seeds=sd[pick],
+                         step0=7)
+    err = wrapdiff(got[pick], want).max()
+    bound = _bf16x3_bound(Jd, K, steps)
+    print(f"dense n={n} R={R} replica {pick}: max |dtheta| = {err:.3e} rad "
+          f"(split bound {bound:.2e})", flush=True)
+    assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+    assert err < max(1e-5, 20 * bound)
