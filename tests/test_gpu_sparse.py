@@ -93,7 +93,7 @@ def test_potts_colouring_parity_ragged(dev, oim, orc):
                   use=100)
 
 
-@pytest.mark.parametrize("q", [4, 5])
+@pytest.mark.parametrize("q", [4, 5, 16])
 def test_generic_q_parity(dev, oim, orc, q):
     g = synth.random_small(97, 0.08, seed=q, weights="real")
     _check_parity(orc, oim, g, -g.w, q=q, R=2, steps_total=1000, use=100)
@@ -288,6 +288,29 @@ def test_stepwise_parity(dev, oim, orc):
         print(f"stepwise n={g.n} q={q} R={R}: max |dtheta| = {err:.3e} rad", flush=True)
         assert err < TOL_RAD
         prob.close()
+
+
+def test_graph_beyond_lds_runs_stepwise(dev, oim, orc):
+    # a 200 x 300 torus (n = 60000) does not fit one workgroup's LDS: the
+    # persistent loop is refused with an error, the automatic choice runs the
+    # stepwise loop, and two sampled replicas of eight match the oracle
+    g = synth.torus(200, 300, seed=8)
+    prob = _problem(oim, g, -g.w)
+    K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 2, 2000, 100)
+    R = 8
+    th0 = synth.theta0(R, g.n, seed=32)
+    sd = synth.seeds(R, 6)
+    with pytest.raises(oim.OimError):
+        _gpu_run(oim, prob, th0, K, Ks, sg, sd, 2, flags=oim.OIM_LOOP_PERSISTENT)
+    got, _ = _gpu_run(oim, prob, th0, K, Ks, sg, sd, 2, step0=3)
+    pick = [0, R - 1]
+    want = orc.run_csr(g.row_ptr, g.col, -g.w, th0[pick], q=2, dt=DT, K=K, Ks=Ks, sigma=sg,
+                       seeds=sd[pick], step0=3)
+    err = wrapdiff(got[pick], want).max()
+    print(f"stepwise n={g.n} R={R} replicas {pick}: max |dtheta| = {err:.3e} rad", flush=True)
+    assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+    assert err < TOL_RAD
+    prob.close()
 
 
 def test_stepwise_readout_and_resume(dev, oim, orc):
