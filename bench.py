@@ -209,6 +209,31 @@ def bench_dense(args, n=4096):
     prob.close()
 
 
+SEED_SETS = 5
+
+
+def _one_flip_descent(g, colour):
+    """Cut after greedy single-vertex flips from a 0/1 state until no flip
+    raises the cut (host, for the reference value only)."""
+    s = np.asarray(colour, np.int8).copy()
+    rows = np.repeat(np.arange(g.n), np.diff(g.row_ptr))
+    w = g.w.astype(np.float64)
+    same = s[rows] == s[g.col]
+    gain = np.zeros(g.n)
+    np.add.at(gain, rows, np.where(same, w, -w))  # cut change if vertex flips
+    for _ in range(10 * g.n):
+        i = int(np.argmax(gain))
+        if gain[i] <= 1e-12:
+            break
+        s[i] ^= 1
+        gain[i] = -gain[i]
+        for e in range(g.row_ptr[i], g.row_ptr[i + 1]):
+            j = g.col[e]
+            gain[j] += 2.0 * w[e] if s[i] == s[j] else -2.0 * w[e]
+    iu, ju, wu = g.upper_edges()
+    return float(np.sum(wu[s[iu] != s[ju]]))
+
+
 def _sync_time(fn):
     import torch
     torch.cuda.synchronize()
@@ -581,27 +606,62 @@ def main():
     value = eu_per_solve / (ms_per_step * 1e-3)
 
     # ---- time to 99 % of the best cut, batched vs plain ----
-    # best_ref: best cut of the timed solves and of one 10x longer reference
-    # run (same schedule shape stretched, other seeds), untimed.
+    # best_ref: the best cut of the timed solves, of four more seed sets, of
+    # one 10x longer reference run (same schedule shape stretched, other
+    # seeds), all untimed, and of a host 1-flip descent from the best state.
     W = -prob.info["sum_J_upper"]
-    tr = trace.cpu().numpy()
-    cut_trace = (W - tr) / 2.0                       # [readouts][R]
     final_cut = int(max(int(c.max()) for c in cuts))
-    best_ref = max(float(cut_trace.max()), float(final_cut))
+    sets = [((W - trace.cpu().numpy()) / 2.0, None)]  # [readouts][R] cut traces
+    best_cut_seen, best_state = -np.inf, None
+    for k in range(SEED_SETS):
+        th_k = torch.from_numpy(synth.theta0(R, g.n, seed=100 + k)).to(dev)
+        sd_k = torch.from_numpy(synth.seeds(R, k * 1000003)).to(dev)
+        ro_k = oim.run(prob, th_k, dK, dKs, dsg, sd_k, q=q, dt=dt, readout_every=M,
+                       want_best=True)
+        ct = (W - ro_k["trace"].cpu().numpy()) / 2.0
+        if k > 0:
+            sets.append((ct, None))
+        bh = ro_k["best_h"].cpu().numpy()
+        r_best = int(np.argmin(bh))
+        if (W - bh[r_best]) / 2.0 > best_cut_seen:
+            best_cut_seen = (W - bh[r_best]) / 2.0
+            best_state = ro_k["best_colour"][r_best].cpu().numpy()
+    best_ref = max(max(float(ct.max()) for ct, _ in sets), float(final_cut), best_cut_seen)
     if args.ref_mult > 0:
         rs = steps * args.ref_mult
         rK, rKs, rsg, _, _ = _schedules(wl, prob.info["max_abs_row_sum"], rs, dt)
         th_r = torch.from_numpy(synth.theta0(R, g.n, seed=7)).to(dev)
         sd_r = torch.from_numpy(synth.seeds(R, 1 << 20)).to(dev)
         ro_r = oim.run(prob, th_r, torch.from_numpy(rK).to(dev), torch.from_numpy(rKs).to(dev),
-                       torch.from_numpy(rsg).to(dev), sd_r, q=q, dt=dt, readout_every=M)
-        best_ref = max(best_ref, float((W - ro_r["best_h"].min().item()) / 2.0))
+                       torch.from_numpy(rsg).to(dev), sd_r, q=q, dt=dt, readout_every=M,
+                       want_best=True)
+        bh = ro_r["best_h"].cpu().numpy()
+        r_best = int(np.argmin(bh))
+        if (W - bh[r_best]) / 2.0 > best_cut_seen:
+            best_cut_seen = (W - bh[r_best]) / 2.0
+            best_state = ro_r["best_colour"][r_best].cpu().numpy()
+        best_ref = max(best_ref, best_cut_seen)
+    polished = _one_flip_descent(g, best_state) if best_state is not None else None
+    if polished is not None:
+        best_ref = max(best_ref, polished)
     target = 0.99 * best_ref
-    best_so_far = np.maximum.accumulate(cut_trace.max(axis=1))
-    hit = np.nonzero(best_so_far >= target)[0]
-    t99_ms = None
-    if hit.size:
-        t99_ms = min((int(hit[0]) + 1) * M, steps) / steps * kern_ms
+    t99s, successes = [], 0
+    for ct, _ in sets:
+        best_so_far = np.maximum.accumulate(ct.max(axis=1))
+        hit = np.nonzero(best_so_far >= target)[0]
+        t99s.append(min((int(hit[0]) + 1) * M, steps) / steps * kern_ms if hit.size else None)
+        successes += int(np.sum(ct.max(axis=0) >= target))
+    t99_ms = t99s[0]
+    t99_median = (float(np.median(t99s)) if all(t is not None for t in t99s) else None)
+    p_success = successes / float(R * len(sets))
+    # time to solution at 99 % confidence for one replica's share of a batched
+    # run (kern_ms / R per replica-run), from the per-replica success rate
+    if p_success >= 1.0:
+        tts99 = kern_ms / R
+    elif p_success > 0.0:
+        tts99 = kern_ms / R * np.log(0.01) / np.log(1.0 - p_success)
+    else:
+        tts99 = None
 
     # plain loop: one launch per replica (R = 1), same schedule and seeds, run
     # one after the other until a replica reaches the target
@@ -651,7 +711,12 @@ def main():
                    "K_max": kmax, "Ks_max": ksmax, "readout_every": M},
         "roofline": roofline,
         "time_to_99pct_best_cut_ms": t99_ms,
-        "best_cut_ref": best_ref, "best_cut_batched": float(cut_trace.max()),
+        "time_to_99pct_best_cut_ms_median_5_seed_sets": t99_median,
+        "time_to_99pct_best_cut_ms_per_seed_set": t99s,
+        "replica_success_rate_99pct": p_success,
+        "tts99_ms_per_replica_run": tts99,
+        "best_cut_ref": best_ref, "best_cut_batched": float(sets[0][0].max()),
+        "best_cut_ref_polish": polished,
         "plain": plain,
     }
     if not args.no_cpu_baseline:
