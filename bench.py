@@ -205,8 +205,47 @@ def bench_dense(args, n=4096):
                      "run_ms": run_ms, "flops_per_step": flops_step},
         "best_energy_per_spin": e_per_spin,
     }
+    if not args.no_cpu_baseline and n == 4096:
+        out["cpu_baseline"] = cpu_baseline_dense(prob, J, th_init, seeds, Kh, Ksh, sgh, q, dt)
     print(json.dumps(out))
     prob.close()
+
+
+def cpu_baseline_dense(prob, J, th_init, seeds, K, Ks, sg, q, dt, target_s=15.0):
+    """The FP64 oracle's all-pairs integrator on a bounded sample of the dense
+    workload (as many replicas as host threads, the first steps of the same
+    schedule), and the GPU's BF16x3 result on the same sample against it."""
+    import torch
+    import oracle
+    import paper_2505_22631_amd as oim
+    n = J.shape[0]
+    threads = max(1, min(16, os.cpu_count() or 1))
+    R = threads
+    Jd = J.astype(np.float64)
+    th0 = th_init[:R].cpu().numpy()
+    sd = seeds[:R].cpu().numpy()
+    t0 = time.perf_counter()
+    oracle.run_dense(Jd, th0, q=q, dt=dt, K=K[:1], Ks=Ks[:1], sigma=sg[:1], seeds=sd,
+                     nthreads=threads)
+    per_step = time.perf_counter() - t0
+    steps = int(max(2, min(len(K), target_s / max(per_step, 1e-9))))
+    t0 = time.perf_counter()
+    want = oracle.run_dense(Jd, th0, q=q, dt=dt, K=K[:steps], Ks=Ks[:steps],
+                            sigma=sg[:steps], seeds=sd, nthreads=threads)
+    el = time.perf_counter() - t0
+    dev = th_init.device
+    got = th_init[:R].clone()
+    oim.oim_run(prob.handle, n, got, torch.from_numpy(K[:steps].copy()).to(dev),
+                torch.from_numpy(Ks[:steps].copy()).to(dev),
+                torch.from_numpy(sg[:steps].copy()).to(dev), seeds[:R].contiguous(), q=q,
+                dt=dt, flags=oim.OIM_PREC_BF16X3)
+    d = np.abs(got.cpu().numpy().astype(np.float64) - want)
+    err = float(np.max(np.minimum(d, 2 * np.pi - d)))
+    eu = float(n) * (n - 1) * R * steps
+    return {"value": eu / el, "unit": "edge-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{R} replicas x {steps} steps of the same J and schedule "
+                      f"({el:.1f} s, FP64 all-pairs, OpenMP over replicas, {_cpu_model()})",
+            "bf16x3_max_abs_dtheta_vs_fp64_rad": err}
 
 
 SEED_SETS = 5
