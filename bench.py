@@ -573,6 +573,8 @@ def main():
                     help="EM steps per dense solve (0: 1000 at n = 4096, 100 at n = 20000)")
     ap.add_argument("--plain-graphs", type=int, default=32,
                     help="graphs timed in the plain per-graph loop of the batched workloads")
+    ap.add_argument("--stepwise", type=int, default=1,
+                    help="also time one torus solve on the stepwise hipGraph loop (0: skip)")
     ap.add_argument("--ref-mult", type=int, default=10,
                     help="length multiple of the untimed reference run that sets best_ref")
     args = ap.parse_args()
@@ -730,6 +732,22 @@ def main():
         plain = {"eu_per_s": float(g.nnz) * steps / pl, "ms_per_replica": pl * 1e3,
                  "replicas_timed": args.plain, "time_to_99pct_best_cut_ms": t99_plain}
 
+    # the same solve on the stepwise loop (state in device memory, chunks of
+    # steps replayed from captured hipGraphs), as the alternative step-loop form
+    stepwise = None
+    if args.workload == "torus" and args.stepwise:
+        th_s = th_init.clone()
+        oim.oim_run(prob.handle, g.n, th_s, dK[:200].contiguous(), dKs[:200].contiguous(),
+                    dsg[:200].contiguous(), seeds, q=q, dt=dt, flags=oim.OIM_LOOP_STEPWISE)
+
+        def solve_stepwise():
+            th_s.copy_(th_init)
+            oim.oim_run(prob.handle, g.n, th_s, dK, dKs, dsg, seeds, q=q, dt=dt,
+                        readout_every=M, trace=trace, flags=oim.OIM_LOOP_STEPWISE)
+        el = _sync_time(solve_stepwise)
+        stepwise = {"ms_per_solve": el * 1e3, "eu_per_s": eu_per_solve / el,
+                    "speedup_persistent": el * 1e3 / ms_per_step}
+
     bytes_per_step = 8.0 * g.n * R + 8.0 * g.nnz + 4.0 * (g.n + 1)
     achieved = bytes_per_step * steps / (kern_ms * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -757,6 +775,7 @@ def main():
         "best_cut_ref": best_ref, "best_cut_batched": float(sets[0][0].max()),
         "best_cut_ref_polish": polished,
         "plain": plain,
+        "stepwise_hipgraph_loop": stepwise,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -122,6 +122,30 @@ def test_full_width_sampled_replicas(dev, oim, orc):
         assert wrapdiff(got[r:r + 1], want).max() < TOL_RAD
 
 
+def test_largest_lds_resident_graph(dev, oim, orc):
+    # a 120 x 150 torus (n = 18000, 71 slices of 256 oscillators) is close to
+    # the largest replica that fits one workgroup's LDS; it must run on the
+    # LDS-resident loop (requested explicitly) and match the oracle on two
+    # sampled replicas of 16, readout included
+    g = synth.torus(120, 150, seed=9)
+    prob = _problem(oim, g, -g.w)
+    K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 2, 1000, 100)
+    R = 16
+    th0 = synth.theta0(R, g.n, seed=33)
+    sd = synth.seeds(R, 12)
+    got, ro = _gpu_run(oim, prob, th0, K, Ks, sg, sd, 2, readout_every=25,
+                       flags=oim.OIM_LOOP_PERSISTENT)
+    pick = [0, R - 1]
+    want = orc.run_csr(g.row_ptr, g.col, -g.w, th0[pick], q=2, dt=DT, K=K, Ks=Ks, sigma=sg,
+                       seeds=sd[pick])
+    err = wrapdiff(got[pick], want).max()
+    print(f"persistent n={g.n} R={R} replicas {pick}: max |dtheta| = {err:.3e} rad", flush=True)
+    assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+    assert err < TOL_RAD
+    assert ro["trace"].shape[0] == 4 and np.all(np.isfinite(ro["trace"]))
+    prob.close()
+
+
 def test_resume_and_determinism_bit_exact(dev, oim, orc):
     g = c2_graph()
     prob = _problem(oim, g, -g.w)
