@@ -149,6 +149,43 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
     const int64_t e0 = g.begin(i), e1 = g.end(i);
     float A0 = 0.f, B0 = 0.f, C0 = 0.f, D0 = 0.f, A1 = 0.f, B1 = 0.f, C1 = 0.f, D1 = 0.f;
     int64_t e = e0;
+    // eight edges at a time: eight index reads, then eight table reads, in
+    // flight together; edges at even offsets from e0 go to the first partial
+    // sums and odd ones to the second, in order, exactly as in the pairwise
+    // loop below, so the sums do not depend on the unrolling
+    for (; e + 8 <= e1; e += 8) {
+        int jj[8];
+        float ww[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) g.edge(e + k, jj[k], ww[k]);
+        if constexpr (LAM) {
+            float4 pv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pv[k] = tab[jj[k]];
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                A0 = __builtin_fmaf(ww[k], pv[k].y, A0);
+                B0 = __builtin_fmaf(ww[k], pv[k].x, B0);
+                C0 = __builtin_fmaf(ww[k], pv[k].w, C0);
+                D0 = __builtin_fmaf(ww[k], pv[k].z, D0);
+                A1 = __builtin_fmaf(ww[k + 1], pv[k + 1].y, A1);
+                B1 = __builtin_fmaf(ww[k + 1], pv[k + 1].x, B1);
+                C1 = __builtin_fmaf(ww[k + 1], pv[k + 1].w, C1);
+                D1 = __builtin_fmaf(ww[k + 1], pv[k + 1].z, D1);
+            }
+        } else {
+            float2 pv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) pv[k] = *reinterpret_cast<const float2*>(tab + jj[k]);
+#pragma unroll
+            for (int k = 0; k < 8; k += 2) {
+                A0 = __builtin_fmaf(ww[k], pv[k].y, A0);
+                B0 = __builtin_fmaf(ww[k], pv[k].x, B0);
+                A1 = __builtin_fmaf(ww[k + 1], pv[k + 1].y, A1);
+                B1 = __builtin_fmaf(ww[k + 1], pv[k + 1].x, B1);
+            }
+        }
+    }
     for (; e + 2 <= e1; e += 2) {
         int j0, j1;
         float w0, w1;
