@@ -68,33 +68,55 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const uint64_t seed = r < a.R ? a.seeds[r] : 0ull;
     float z[4];
     normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
+    // The quad's four rows are walked in lock-step, two edges of each per
+    // iteration, so eight neighbour loads are in flight together.  Row
+    // lengths are wave-uniform (every lane is a replica of the same quad), so
+    // a row that is shorter than the longest costs only its idle slots, which
+    // load the quad's own entry with weight 0 and leave the sums unchanged
+    // (the table holds finite values).  Each row keeps its order: edges at
+    // even offsets into one partial sum, odd ones into the other.
+    int64_t eb[4];
+    int len[4];
+    int lmax = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        const int i = 4 * m + j;
+        const bool ok = i < a.n;
+        eb[j] = ok ? a.row_ptr[i] : 0;
+        len[j] = ok ? (int)(a.row_ptr[i + 1] - eb[j]) : 0;
+        lmax = len[j] > lmax ? len[j] : lmax;
+    }
+    float A0[4], B0[4], A1[4], B1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) A0[j] = B0[j] = A1[j] = B1[j] = 0.f;
+    for (int t = 0; t < lmax; t += 2) {
+        float2 p[4][2];
+        float w[4][2];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const bool ok = t + h < len[j];
+                const int64_t e = ok ? eb[j] + t + h : 0;
+                const int c = ok ? a.col[e] : 4 * m;
+                w[j][h] = ok ? a.J[e] : 0.f;
+                p[j][h] = a.tin[(size_t)c * Rp + r];
+            }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            A0[j] = __builtin_fmaf(w[j][0], p[j][0].y, A0[j]);
+            B0[j] = __builtin_fmaf(w[j][0], p[j][0].x, B0[j]);
+            A1[j] = __builtin_fmaf(w[j][1], p[j][1].y, A1[j]);
+            B1[j] = __builtin_fmaf(w[j][1], p[j][1].x, B1[j]);
+        }
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int i = 4 * m + j;
         if (i >= a.n) break;
-        const int64_t e0 = a.row_ptr[i], e1 = a.row_ptr[i + 1];
-        float A0 = 0.f, B0 = 0.f, A1 = 0.f, B1 = 0.f;
-        int64_t e = e0;
-        for (; e + 2 <= e1; e += 2) {
-            const int c0 = a.col[e], c1 = a.col[e + 1];
-            const float w0 = a.J[e], w1 = a.J[e + 1];
-            const float2 p0 = a.tin[(size_t)c0 * Rp + r];
-            const float2 p1 = a.tin[(size_t)c1 * Rp + r];
-            A0 = __builtin_fmaf(w0, p0.y, A0);
-            B0 = __builtin_fmaf(w0, p0.x, B0);
-            A1 = __builtin_fmaf(w1, p1.y, A1);
-            B1 = __builtin_fmaf(w1, p1.x, B1);
-        }
-        if (e < e1) {
-            const int c0 = a.col[e];
-            const float w0 = a.J[e];
-            const float2 p0 = a.tin[(size_t)c0 * Rp + r];
-            A0 = __builtin_fmaf(w0, p0.y, A0);
-            B0 = __builtin_fmaf(w0, p0.x, B0);
-        }
         const size_t idx = (size_t)i * Rp + r;
         const float2 own = a.tin[idx];
-        const float A = A0 + A1, B = B0 + B1;
+        const float A = A0[j] + A1[j], B = B0[j] + B1[j];
         const float coup = own.x * A - own.y * B;
         const uint32_t u0 = a.U[idx];
         const float drift = kc * coup + ks * sin_q<QM>(own.x, own.y, u0, q);
