@@ -138,7 +138,10 @@ def cpu_baseline(wl, target_s=15.0):
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 
 
-def bench_dense(args, n=4096):
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def bench_dense(args, n=4096, fp32=False):
     """Dense SK Ising: J_ij ~ N(0, 1/n) (seed 3), 512 replicas, coupling as a
     BF16x3 GEMM on the matrix cores; n = 4096 (1000 steps) or the paper's
     largest all-to-all size n = 20000 (100 steps)."""
@@ -166,7 +169,7 @@ def bench_dense(args, n=4096):
         if ev:
             ev[0].record(stream)
         oim.oim_run(prob.handle, n, theta, K, Ks, sg, seeds, q=q, dt=dt,
-                    flags=oim.OIM_PREC_BF16X3)
+                    flags=oim.OIM_PREC_FP32 if fp32 else oim.OIM_PREC_BF16X3)
         if ev:
             ev[1].record(stream)
 
@@ -186,32 +189,37 @@ def bench_dense(args, n=4096):
     col = oim.oim_round(q, theta)
     hm, _ = oim.oim_energy(prob.handle, q, colour=col)
     e_per_spin = float(hm.min().item()) / n
-    # executed MFMA flops of the BF16x3 coupling: 3 products of an n x n by
-    # n x 2R GEMM per step
-    flops_step = 3.0 * 2.0 * n * n * 2 * R
+    # executed MFMA flops per step: 3 products of an n x n by n x 2R GEMM for
+    # the BF16x3 coupling, one FP32 product for the FP32 coupling
+    flops_step = (1.0 if fp32 else 3.0) * 2.0 * n * n * 2 * R
+    peak = MFMA_FP32_PEAK_TFLOPS if fp32 else MFMA_BF16_PEAK_TFLOPS
     achieved = flops_step * steps / (run_ms * 1e-3) / 1e12
     out = {
         "metric": "edge-updates/s & time-to-99%-best-cut, batched vs plain, 1 MI355X",
         "value": eu / (ms_per_step * 1e-3), "unit": "edge-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16x3",
-        "data": "synthetic",
-        "config": {"workload": f"dense SK Ising n={n}, 512 replicas, BF16x3 MFMA coupling",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if fp32 else "bf16x3", "data": "synthetic",
+        "config": {"workload": f"dense SK Ising n={n}, 512 replicas, "
+                               f"{'FP32' if fp32 else 'BF16x3'} MFMA coupling",
                    "n": n, "replicas": R, "em_steps": steps, "K_max": kmax, "Ks_max": ksmax},
-        "roofline": {"bound": "mfma", "achieved": achieved, "peak": MFMA_BF16_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / MFMA_BF16_PEAK_TFLOPS,
-                     "traffic": _measured_traffic(DENSE_PROFILE, DENSE_SOURCES),
-                     "kernel": "dense_step_kernel (per run, incl. epilogue)",
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
+                     "unit": "TFLOP/s", "frac": achieved / peak,
+                     "traffic": (None if fp32 else
+                                 _measured_traffic(DENSE_PROFILE, DENSE_SOURCES)),
+                     "kernel": ("dense_step32_kernel" if fp32 else "dense_step_kernel")
+                               + " (per run, incl. epilogue)",
                      "run_ms": run_ms, "flops_per_step": flops_step},
         "best_energy_per_spin": e_per_spin,
     }
     if not args.no_cpu_baseline and n == 4096:
-        out["cpu_baseline"] = cpu_baseline_dense(prob, J, th_init, seeds, Kh, Ksh, sgh, q, dt)
+        out["cpu_baseline"] = cpu_baseline_dense(prob, J, th_init, seeds, Kh, Ksh, sgh, q, dt,
+                                                 fp32=fp32)
     print(json.dumps(out))
     prob.close()
 
 
-def cpu_baseline_dense(prob, J, th_init, seeds, K, Ks, sg, q, dt, target_s=15.0):
+def cpu_baseline_dense(prob, J, th_init, seeds, K, Ks, sg, q, dt, target_s=15.0, fp32=False):
     """The FP64 oracle's all-pairs integrator on a bounded sample of the dense
     workload (as many replicas as host threads, the first steps of the same
     schedule), and the GPU's BF16x3 result on the same sample against it."""
@@ -238,14 +246,14 @@ def cpu_baseline_dense(prob, J, th_init, seeds, K, Ks, sg, q, dt, target_s=15.0)
     oim.oim_run(prob.handle, n, got, torch.from_numpy(K[:steps].copy()).to(dev),
                 torch.from_numpy(Ks[:steps].copy()).to(dev),
                 torch.from_numpy(sg[:steps].copy()).to(dev), seeds[:R].contiguous(), q=q,
-                dt=dt, flags=oim.OIM_PREC_BF16X3)
+                dt=dt, flags=oim.OIM_PREC_FP32 if fp32 else oim.OIM_PREC_BF16X3)
     d = np.abs(got.cpu().numpy().astype(np.float64) - want)
     err = float(np.max(np.minimum(d, 2 * np.pi - d)))
     eu = float(n) * (n - 1) * R * steps
     return {"value": eu / el, "unit": "edge-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{R} replicas x {steps} steps of the same J and schedule "
                       f"({el:.1f} s, FP64 all-pairs, OpenMP over replicas, {_cpu_model()})",
-            "bf16x3_max_abs_dtheta_vs_fp64_rad": err}
+            ("fp32" if fp32 else "bf16x3") + "_max_abs_dtheta_vs_fp64_rad": err}
 
 
 SEED_SETS = 5
@@ -565,7 +573,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="torus",
-                    choices=["torus", "gnp800", "sk4096", "sk20000", "colouring", "adjoint", "sweep"])
+                    choices=["torus", "gnp800", "sk4096", "sk4096_fp32", "sk20000", "colouring",
+                             "adjoint", "sweep"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", type=int, default=8,
                     help="replicas to time in the plain one-launch-per-replica loop")
@@ -588,6 +597,8 @@ def main():
         return bench_dense(args)
     if args.workload == "sk20000":
         return bench_dense(args, n=20000)
+    if args.workload == "sk4096_fp32":
+        return bench_dense(args, fp32=True)
     if args.workload == "colouring":
         return bench_colouring(args)
     if args.workload == "adjoint":

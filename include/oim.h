@@ -134,7 +134,7 @@ int oim_problem_info_get(oim_problem p, oim_problem_info* info);
 #define OIM_LOOP_PERSISTENT  0x1u  /* one launch, replica state resident in LDS      */
 #define OIM_LOOP_STEPWISE    0x2u  /* one kernel per step, state in device memory    */
 #define OIM_LOOP_MASK        0x3u
-#define OIM_PREC_FP32        0x0u  /* FP32 coupling sum                              */
+#define OIM_PREC_FP32        0x0u  /* FP32 coupling sum (dense: FP32 products on MFMA) */
 #define OIM_PREC_BF16X3      0x10u /* dense only: BF16 three-term split on MFMA       */
 #define OIM_PREC_MASK        0x30u
 #define OIM_SCHED_PER_REPLICA 0x100u /* K, Ks, sigma are [R][steps]: one schedule per  */

@@ -302,6 +302,217 @@ void dense_step_kernel(DenseArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// FP32 coupling (OIM_PREC_FP32): the same product Y = J [S | C] with FP32
+// operands on v_mfma_f32_16x16x4_f32 (FP32 products, FP32 accumulation: the
+// paper's own precision), same workgroup tile, same stage size (32 K values of
+// FP32 = 32 KiB of J and X per stage), same DMA ring and barriers.
+//
+// Image layout: a row of one stage block holds 32 FP32 values (128 bytes).
+// MFMA K-step kk (0..7) of a stage takes K index 4 kk + g in lane group
+// g = lane / 16, so the values are stored K-permuted, position 8 g + kk holding
+// K index 4 kk + g: each lane group's 8 values of a stage are 32 contiguous
+// bytes (two 16-byte reads).  The permutation is the same for J's columns and
+// X's rows, so the product is the same sum over K.  The eight 16-byte
+// segments of a row are XOR-swizzled by (row / 2) % 8, which spreads the 16
+// rows one lane group reads over all banks.
+//   J: block (row tile ti, stage kc) at (ti * nk + kc) * 16 KiB, 128 rows;
+//   X: block (replica tile tr, stage kc) at (tr * nk + kc) * 16 KiB, S rows
+//      (64) then C rows (64).
+constexpr int kRow32 = kTK * 4;  // bytes per FP32 row
+
+__device__ __forceinline__ int swz32(int row, int seg) {
+    return row * kRow32 + ((seg ^ ((row >> 1) & 7)) << 4);
+}
+// byte offset of (row rr, K index kk) inside a block region
+__device__ __forceinline__ int tile_off32(int rr, int kk) {
+    const int pos = (kk & 3) * 8 + (kk >> 2);
+    return swz32(rr, pos >> 2) + (pos & 3) * 4;
+}
+
+template <int QM>
+__global__ __launch_bounds__(kTB) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void dense_step32_kernel(DenseArgs a) {
+    __shared__ __align__(1024) unsigned char lds[kDepth][kStageBytes];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int i0 = blockIdx.x * kTM, r0 = blockIdx.y * kTR;
+    const int np = a.np;
+
+    const unsigned char* src = wave < 2
+        ? a.Jt + (size_t)blockIdx.x * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
+        : a.Xin + (size_t)blockIdx.y * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
+    auto issue = [&](int kc, int buf) __attribute__((always_inline)) {
+        unsigned char* dst = lds[buf] + wave * kWaveChunks * 1024;
+        const unsigned char* sp = src + (size_t)kc * kBlock;
+#pragma unroll
+        for (int x = 0; x < kWaveChunks; ++x)
+            __builtin_amdgcn_global_load_lds((glb_void_t*)(sp + x * 1024),
+                                             (lds_void_t*)(dst + x * 1024), 16, 0, 0);
+    };
+
+    f32x4 acc[4][2][2];  // [row block][replica block][S, C]
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int c = 0; c < 2; ++c) acc[b][c][0] = acc[b][c][1] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    const int nk = a.nk;
+    const int frow = lane & 15, g = lane >> 4;
+    // lane group g's 8 values of a row: segments 2g and 2g + 1
+    struct Frags32 {
+        f32x4 a[4][2];      // J, 4 row blocks
+        f32x4 b[2][2][2];   // X [replica block][S, C]
+    };
+    auto read_frags = [&](const unsigned char* base, Frags32& f) __attribute__((always_inline)) {
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+            const int row = wn * 32 + cb * 16 + frow;
+#pragma unroll
+            for (int sc = 0; sc < 2; ++sc) {
+                const unsigned char* bb = base + kTM * kRow32 + sc * kTR * kRow32;
+                f.b[cb][sc][0] = *reinterpret_cast<const f32x4*>(bb + swz32(row, 2 * g));
+                f.b[cb][sc][1] = *reinterpret_cast<const f32x4*>(bb + swz32(row, 2 * g + 1));
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int row = wm * 64 + b * 16 + frow;
+            f.a[b][0] = *reinterpret_cast<const f32x4*>(base + swz32(row, 2 * g));
+            f.a[b][1] = *reinterpret_cast<const f32x4*>(base + swz32(row, 2 * g + 1));
+        }
+    };
+    auto mfmas = [&](const Frags32& f) __attribute__((always_inline)) {
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk)
+#pragma unroll
+            for (int b = 0; b < 4; ++b)
+#pragma unroll
+                for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+                    for (int sc = 0; sc < 2; ++sc)
+                        acc[b][cb][sc] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            f.a[b][kk >> 2][kk & 3], f.b[cb][sc][kk >> 2][kk & 3], acc[b][cb][sc],
+                            0, 0, 0);
+    };
+    auto stage = [&](int kc, Frags32& cur, Frags32& nxt) __attribute__((always_inline)) {
+        __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 3) * kWaveChunks));
+        lds_barrier();
+        read_frags(lds[(kc + 1) % kDepth], nxt);
+        issue(kc + kDepth - 1 < nk ? kc + kDepth - 1 : nk - 1, (kc + kDepth - 1) % kDepth);
+        mfmas(cur);
+    };
+
+#pragma unroll
+    for (int d = 0; d < kDepth - 1; ++d) issue(d, d);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm((kDepth - 2) * kWaveChunks));
+    lds_barrier();
+    Frags32 F0, F1;
+    read_frags(lds[0], F0);
+    for (int kc = 0; kc < nk - 2; kc += 2) {
+        stage(kc, F0, F1);
+        stage(kc + 1, F1, F0);
+    }
+    stage(nk - 2, F0, F1);
+    const int qi0 = i0 + wm * 64 + 4 * (lane >> 4);
+    uint4 uq[2][4];
+    uint64_t seedv[2];
+    float sK[2], sKs[2], sS[2];
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
+        seedv[cb] = r < a.R ? a.seeds[r] : 0ull;
+        const int64_t so = (int64_t)(r < a.R ? r : 0) * a.sched_stride + a.s;
+        sK[cb] = a.K[so];
+        sKs[cb] = a.Ks[so];
+        sS[cb] = a.sigma[so];
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+            uq[cb][b] = *reinterpret_cast<const uint4*>(a.U + (size_t)r * np + qi0 + b * 16);
+    }
+    mfmas(F1);
+    __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
+
+    // ---- epilogue: SHIL, noise, Euler-Maruyama update, next [S | C] ----
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+        const int r = r0 + wn * 32 + cb * 16 + (lane & 15);
+        const bool rvalid = r < a.R;
+        const float kcoef = -a.dt * sK[cb] * kTurnScale;
+        const float kscoef = -a.dt * sKs[cb] * kTurnScale;
+        const float nscoef = sS[cb] * a.sqrt_dt * kTurnScale;
+        const uint32_t k0 = (uint32_t)seedv[cb], k1 = (uint32_t)(seedv[cb] >> 32);
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int i = qi0 + b * 16;
+            if (!rvalid || i >= a.n) continue;
+            uint32_t u[4] = {uq[cb][b].x, uq[cb][b].y, uq[cb][b].z, uq[cb][b].w};
+            float z[4];
+            normals4((uint32_t)(i >> 2), a.t, 0u, k0, k1, z);
+            float s1[4], c1[4];
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const float s0 = sin_turn(u[x]), c0 = cos_turn(u[x]);
+                const float coup = s0 * acc[b][cb][1][x] - c0 * acc[b][cb][0][x];
+                const float drift = kcoef * coup + kscoef * sin_q<QM>(s0, c0, u[x], a.q);
+                if (i + x < a.n) u[x] = advance(u[x], __builtin_fmaf(nscoef, z[x], drift));
+                s1[x] = i + x < a.n ? sin_turn(u[x]) : 0.f;
+                c1[x] = i + x < a.n ? cos_turn(u[x]) : 0.f;
+            }
+            *reinterpret_cast<uint4*>(a.U + (size_t)r * np + i) = uint4{u[0], u[1], u[2], u[3]};
+            unsigned char* xo = a.Xout + ((size_t)(r >> 6) * a.nk + (i >> 5)) * kBlock;
+#pragma unroll
+            for (int x = 0; x < 4; ++x) {
+                const int off = tile_off32(r & 63, (i & 31) + x);
+                *reinterpret_cast<float*>(xo + off) = s1[x];
+                *reinterpret_cast<float*>(xo + kTR * kRow32 + off) = c1[x];
+            }
+        }
+    }
+}
+
+// Phase words and FP32 [S | C] of the initial state in the FP32 image layout.
+__global__ __launch_bounds__(256) void dense_init32_kernel(const float* theta, const uint32_t* phase,
+                                                           uint32_t* U, unsigned char* X,
+                                                           unsigned char* X2, int n, int R, int np,
+                                                           int Rp) {
+    const size_t plane = (size_t)Rp * np;
+    const int nk = np / kTK;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < plane;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int r = (int)(e / np), i = (int)(e % np);
+        uint32_t u = 0;
+        float s = 0.f, c = 0.f;
+        if (r < R && i < n) {
+            const size_t src = (size_t)r * n + i;
+            u = phase ? phase[src] : phase_from_theta(theta[src]);
+            s = sin_turn(u);
+            c = cos_turn(u);
+        }
+        U[e] = u;
+        const size_t o = ((size_t)(r >> 6) * nk + (i >> 5)) * kBlock + tile_off32(r & 63, i & 31);
+        *reinterpret_cast<float*>(X + o) = s;
+        *reinterpret_cast<float*>(X + o + kTR * kRow32) = c;
+        *reinterpret_cast<float*>(X2 + o) = s;
+        *reinterpret_cast<float*>(X2 + o + kTR * kRow32) = c;
+    }
+}
+
+// J -> FP32 image with the diagonal and the padding zeroed.
+__global__ __launch_bounds__(256) void dense_tile32_kernel(const float* J, unsigned char* Jt, int n,
+                                                           int np) {
+    const size_t total = (size_t)np * np;
+    const int nk = np / kTK;
+    for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (size_t)gridDim.x * blockDim.x) {
+        const int i = (int)(e / np), j = (int)(e % np);
+        const float v = (i < n && j < n && i != j) ? J[(size_t)i * n + j] : 0.f;
+        const size_t o = ((size_t)(i / kTM) * nk + j / kTK) * kBlock + tile_off32(i % kTM, j % kTK);
+        *reinterpret_cast<float*>(Jt + o) = v;
+    }
+}
+
 // Phase words and split [S | C] of the initial state, written to both
 // ping-pong sets; padding rows and replicas get X = 0 in both (they add
 // nothing to any coupling sum and the step kernel never writes them).
@@ -449,22 +660,32 @@ int dense_prepare(Problem* p, const float* J) {
 void dense_release(Problem* p) {
     hipFree(p->d_Jdense);
     hipFree(p->d_Jtiled);
+    hipFree(p->d_Jtiled32);
     p->d_Jdense = nullptr;
     p->d_Jtiled = nullptr;
+    p->d_Jtiled32 = nullptr;
 }
 
 int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                  const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
                  uint32_t* phase, const oim_readout* ro, hipStream_t stream) {
-    if ((cfg->flags & OIM_PREC_MASK) != OIM_PREC_BF16X3)
-        return set_error(OIM_E_UNSUPPORTED, "dense problems run with OIM_PREC_BF16X3");
+    const bool fp32 = (cfg->flags & OIM_PREC_MASK) == OIM_PREC_FP32;
     const int n = p->n, R = cfg->R;
     const int np = (n + kTM - 1) / kTM * kTM;
+    if (fp32 && !p->d_Jtiled32) {
+        // the FP32 image of J, made once per problem on the caller's stream
+        int st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jtiled32),
+                               (size_t)np * np * sizeof(float), "FP32 tiled J");
+        if (st) return st;
+        hipLaunchKernelGGL(dense_tile32_kernel, dim3(4096), dim3(256), 0, stream, p->d_Jdense,
+                           p->d_Jtiled32, n, np);
+        if ((st = check_launch("dense_tile32_kernel"))) return st;
+    }
     const int Rp = (R + kTR - 1) / kTR * kTR;
     const size_t plane = (size_t)Rp * np;
     const int M = cfg->readout_every;
     const int nread = M > 0 ? (cfg->steps + M - 1) / M : 0;
-    // workspace: U (4 B) + two X sets (4 x 2 B each) per slot, then readout
+    // workspace: U (4 B) + two X sets (8 B each: 4 x BF16 or 2 x FP32) per slot, then readout
     // scratch: H[R], best tmp [R] (f64), best step [R]
     const size_t need = plane * 4 + 2 * 4 * plane * 2 + (size_t)R * 8 * 2 + (size_t)R * 4 + 256;
     if (p->work_bytes < need) {
@@ -483,14 +704,23 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     double* btmp = H + R;
     int32_t* bstep = reinterpret_cast<int32_t*>(btmp + R);
 
-    hipLaunchKernelGGL(dense_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U, X0, X1,
-                       n, R, np, Rp);
+    if (fp32)
+        hipLaunchKernelGGL(dense_init32_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U,
+                           X0, X1, n, R, np, Rp);
+    else
+        hipLaunchKernelGGL(dense_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U, X0,
+                           X1, n, R, np, Rp);
     int st = check_launch("dense_init_kernel");
     if (st) return st;
-    StepFn fn = cfg->q == 2 ? dense_step_kernel<2> : cfg->q == 3 ? dense_step_kernel<3>
-                                                                   : dense_step_kernel<0>;
+    StepFn fn;
+    if (fp32)
+        fn = cfg->q == 2 ? dense_step32_kernel<2> : cfg->q == 3 ? dense_step32_kernel<3>
+                                                                : dense_step32_kernel<0>;
+    else
+        fn = cfg->q == 2 ? dense_step_kernel<2> : cfg->q == 3 ? dense_step_kernel<3>
+                                                              : dense_step_kernel<0>;
     DenseArgs a{};
-    a.Jt = p->d_Jtiled;
+    a.Jt = fp32 ? p->d_Jtiled32 : p->d_Jtiled;
     a.nk = np / kTK;
     a.U = U;
     a.seeds = seeds;

@@ -71,6 +71,7 @@ struct Problem {
     // device: dense coupling (dense problems), FP32 and the BF16 split
     float* d_Jdense = nullptr;
     unsigned char* d_Jtiled = nullptr;  // J_hi / J_lo in per-stage tiles
+    unsigned char* d_Jtiled32 = nullptr;  // FP32 J in per-stage tiles (made on first FP32 run)
 
     // cached workspace for the stepwise / dense loops
     void* d_work = nullptr;

@@ -19,13 +19,15 @@ def oim():
     return m
 
 
-def _run(oim, prob, th0, K, Ks, sg, sd, q, step0=0, readout_every=0, want_best=False):
+def _run(oim, prob, th0, K, Ks, sg, sd, q, step0=0, readout_every=0, want_best=False,
+         flags=None):
     import torch
     t = torch.from_numpy(np.ascontiguousarray(th0)).cuda()
     out = oim.run(prob, t, torch.from_numpy(K).cuda(), torch.from_numpy(Ks).cuda(),
                   torch.from_numpy(sg).cuda(),
                   torch.from_numpy(np.ascontiguousarray(sd, np.uint64)).cuda(), q=q, dt=DT,
-                  readout_every=readout_every, flags=oim.OIM_PREC_BF16X3, step0=step0,
+                  readout_every=readout_every,
+                  flags=oim.OIM_PREC_BF16X3 if flags is None else flags, step0=step0,
                   want_best=want_best)
     torch.cuda.synchronize()
     return t.cpu().numpy(), {k: v.cpu().numpy() for k, v in out.items()}
@@ -96,7 +98,7 @@ def test_dense_in_run_readout(oim, orc):
         assert abs(h - ro["best_h"][r]) < 1e-9 * max(1.0, np.abs(J).sum())
 
 
-def test_dense_rejects_fp32_precision(oim):
+def test_dense_rejects_unknown_precision(oim):
     import torch
     J = synth.sk_dense(64, seed=1)
     with oim.Problem.from_dense(J) as prob:
@@ -104,7 +106,55 @@ def test_dense_rejects_fp32_precision(oim):
         z = torch.zeros(3, device="cuda")
         with pytest.raises(oim.OimError):
             oim.run(prob, t, z, z, z, torch.zeros(1, dtype=torch.uint64, device="cuda"), q=2,
-                    dt=DT)
+                    dt=DT, flags=0x20)
+
+
+@pytest.mark.parametrize("n,R,q", [(200, 5, 2), (130, 3, 3), (97, 2, 5)])
+def test_dense_fp32_parity(oim, orc, n, R, q):
+    # FP32 products on the matrix cores (OIM_PREC_FP32): the paper's precision,
+    # within the sparse path's tolerance of the FP64 oracle after 100 steps,
+    # and at least as close as the BF16x3 split on the same case
+    J = synth.sk_dense(n, seed=3)
+    with oim.Problem.from_dense(J) as prob:
+        rowsum = prob.info["max_abs_row_sum"]
+        K, Ks, sg = ramp_schedule(rowsum, q, 1000, 100)
+        th0 = synth.theta0(R, n, seed=21)
+        sd = synth.seeds(R, 7)
+        got, _ = _run(oim, prob, th0, K, Ks, sg, sd, q, step0=50, flags=oim.OIM_PREC_FP32)
+        got3, _ = _run(oim, prob, th0, K, Ks, sg, sd, q, step0=50)
+    want = orc.run_dense(J.astype(np.float64), th0, q=q, dt=DT, K=K, Ks=Ks, sigma=sg, seeds=sd,
+                         step0=50)
+    err = wrapdiff(got, want).max()
+    err3 = wrapdiff(got3, want).max()
+    print(f"dense FP32 n={n} R={R} q={q}: max |dtheta| = {err:.3e} rad (BF16x3 {err3:.3e})",
+          flush=True)
+    assert np.all(np.isfinite(got))
+    assert err < 1e-5
+    assert err <= max(err3, 2e-6)
+
+
+def test_dense_fp32_full_size_sampled_replica(oim, orc):
+    # the n = 4096 SK coupling with 128 replicas on the FP32 path; the last
+    # replica checked against the oracle over 5 steps, readout included
+    n, R, steps = 4096, 128, 5
+    J = synth.sk_dense(n, seed=3)
+    with oim.Problem.from_dense(J) as prob:
+        kmax = 32.0 * 0.5 / (DT * prob.info["max_abs_row_sum"])
+        K = synth.ramp(0.0, kmax, 1000)[:steps].copy()
+        Ks = synth.ramp(0.0, 0.03 * 0.5 / (DT * 2), 1000)[:steps].copy()
+        sg = synth.const(0.1, steps)
+        th0 = synth.theta0(R, n, seed=100)
+        sd = synth.seeds(R, 0)
+        got, ro = _run(oim, prob, th0, K, Ks, sg, sd, 2, readout_every=5,
+                       flags=oim.OIM_PREC_FP32)
+    pick = [R - 1]
+    want = orc.run_dense(J.astype(np.float64), th0[pick], q=2, dt=DT, K=K, Ks=Ks, sigma=sg,
+                         seeds=sd[pick])
+    err = wrapdiff(got[pick], want).max()
+    print(f"dense FP32 n=4096 R={R} replica {pick}: max |dtheta| = {err:.3e} rad", flush=True)
+    assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+    assert err < 1e-5
+    assert ro["trace"].shape == (1, R) and np.all(np.isfinite(ro["trace"]))
 
 
 def test_dense_full_size_sampled_replicas(oim, orc):
