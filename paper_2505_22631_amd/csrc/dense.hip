@@ -9,11 +9,13 @@
 // (x = x_hi + x_lo, x_hi = bf16(x), x_lo = bf16(x - x_hi)) and
 //     J X ~ J_hi X_hi + J_hi X_lo + J_lo X_hi
 // is accumulated in FP32 on v_mfma_f32_16x16x32_bf16 (the dropped J_lo X_lo
-// term is ~2^-16 relative).  J's diagonal is zeroed at upload.
+// term is ~2^-16 relative).  With OIM_PREC_FP32 the product runs instead with
+// FP32 operands on v_mfma_f32_16x16x4_f32 (dense_step32_kernel below).  J's
+// diagonal is zeroed at upload.
 //
 // One kernel per Euler-Maruyama step: workgroup tile = 128 rows x 64
 // replicas (S and C columns of the same replicas), 4 waves of 64 rows x 32
-// replicas, K in chunks of 32 staged through LDS (double buffered).  The
+// replicas, K in stages of 32 moved into a ring of 4 LDS buffers.  The
 // epilogue owns, per lane, quads of 4 consecutive rows of one replica -- the
 // MFMA accumulator layout -- so it draws one Philox call per quad, advances
 // the phase words and writes the next step's split [S | C] (ping-pong).
