@@ -134,6 +134,28 @@ def test_noiseless_flow_descends_energy(orc, q):
     assert E[-1] < E[0] - 0.5
 
 
+@pytest.mark.parametrize("q", [2, 3])
+def test_euler_first_order_in_dt(orc, q):
+    # sigma = 0: Algorithm 1 is the explicit Euler method on the flow of
+    # Eq. 5, so the error at a fixed time T falls linearly with the step:
+    # halving dt halves the distance to a 128x finer reference.
+    g = synth.random_small(14, 0.4, seed=21, weights="pm1")
+    J = -g.w.astype(np.float64)
+    K, Ks, T = 1.3, 0.9, 0.64
+    th0 = synth.theta0(1, 14, seed=8).astype(np.float64)
+
+    def run(dt):
+        steps = int(round(T / dt))
+        return orc.run_csr(g.row_ptr, g.col, J, th0, q=q, dt=dt, K=np.full(steps, K),
+                           Ks=np.full(steps, Ks), sigma=np.zeros(steps),
+                           seeds=np.zeros(1, np.uint64))
+    ref = run(0.04 / 128)
+    err = [float(np.max(_wrapdiff(run(dt), ref))) for dt in (0.04, 0.02, 0.01)]
+    assert err[0] > 1e-4  # the step error is visible at the coarsest dt
+    for a, b in zip(err, err[1:]):
+        assert 1.7 < a / b < 2.4, err
+
+
 def test_csr_and_dense_agree(orc):
     g = synth.random_small(12, 0.5, seed=11, weights="real")
     Jd = np.zeros((12, 12))
