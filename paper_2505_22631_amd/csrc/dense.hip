@@ -117,6 +117,19 @@ __device__ __forceinline__ void lds_barrier() {
     asm volatile("" ::: "memory");
 }
 
+// Workgroup -> (row tile, replica tile).  The grid is one-dimensional and
+// consecutive workgroups go to the 8 XCDs in turn, each XCD with its own L2;
+// the tiles are numbered so that XCD c runs a contiguous range of them, row
+// tile major: the replica tiles that share a row tile of J (and read the
+// same J blocks at the same stage) sit on one XCD, in consecutive slots.
+__device__ __forceinline__ void block_tiles(int ntr, int& ti, int& tr) {
+    const int N = (int)gridDim.x, L = (int)blockIdx.x;
+    const int c = L & 7, slot = L >> 3;
+    const int f = c * (N >> 3) + (c < (N & 7) ? c : (N & 7)) + slot;
+    ti = f / ntr;
+    tr = f - ti * ntr;
+}
+
 // One 256-thread workgroup per CU (one wave per SIMD).  Stages move from
 // global memory to LDS with direct DMA loads (global_load_lds_dwordx4: lane
 // l of a wave writes bytes 16l..16l+15 of a 1 KiB LDS chunk), so no staging
@@ -130,7 +143,9 @@ void dense_step_kernel(DenseArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
-    const int i0 = blockIdx.x * kTM, r0 = blockIdx.y * kTR;
+    int ti, tr;
+    block_tiles(a.Rp / kTR, ti, tr);
+    const int i0 = ti * kTM, r0 = tr * kTR;
     const int np = a.np, Rp = a.Rp;
     const size_t plane = (size_t)Rp * np;
 
@@ -138,8 +153,8 @@ void dense_step_kernel(DenseArgs a) {
     // J block of the stage, 16-31 the X block.  Wave w moves chunks
     // 8w..8w+7, lane l the 16 bytes at 16l of each.
     const unsigned char* src = wave < 2
-        ? a.Jt + (size_t)blockIdx.x * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
-        : a.Xin + (size_t)blockIdx.y * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
+        ? a.Jt + (size_t)ti * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
+        : a.Xin + (size_t)tr * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
     auto issue = [&](int kc, int buf) __attribute__((always_inline)) {
         unsigned char* dst = lds[buf] + wave * kWaveChunks * 1024;
         const unsigned char* sp = src + (size_t)kc * kBlock;
@@ -339,12 +354,14 @@ void dense_step32_kernel(DenseArgs a) {
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
-    const int i0 = blockIdx.x * kTM, r0 = blockIdx.y * kTR;
+    int ti, tr;
+    block_tiles(a.Rp / kTR, ti, tr);
+    const int i0 = ti * kTM, r0 = tr * kTR;
     const int np = a.np;
 
     const unsigned char* src = wave < 2
-        ? a.Jt + (size_t)blockIdx.x * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
-        : a.Xin + (size_t)blockIdx.y * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
+        ? a.Jt + (size_t)ti * a.nk * kBlock + wave * kWaveChunks * 1024 + lane * 16
+        : a.Xin + (size_t)tr * a.nk * kBlock + (wave - 2) * kWaveChunks * 1024 + lane * 16;
     auto issue = [&](int kc, int buf) __attribute__((always_inline)) {
         unsigned char* dst = lds[buf] + wave * kWaveChunks * 1024;
         const unsigned char* sp = src + (size_t)kc * kBlock;
@@ -739,7 +756,7 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     a.dt = cfg->dt;
     a.sqrt_dt = std::sqrt(cfg->dt);
     hipError_t e = hipSuccess;
-    dim3 grid(np / kTM, Rp / kTR);
+    dim3 grid((np / kTM) * (Rp / kTR));
     for (int s = 0; s < cfg->steps; ++s) {
         a.Xin = (s & 1) ? X1 : X0;
         a.Xout = (s & 1) ? X0 : X1;
