@@ -30,6 +30,9 @@
 
 #include <cmath>
 
+#include <cstdlib>
+#include <cstring>
+
 #include "internal.hpp"
 #include "noise.hpp"
 #include "phase.hpp"
@@ -45,7 +48,8 @@ namespace {
 constexpr int kAdjTB = 512;
 constexpr int kAdjWaves = kAdjTB / 64;
 constexpr int kAdjQPT = kAdjMaxN / 4 / kAdjTB;  // quads per thread at the size limit
-constexpr int kCsrGlobal = 0, kCsrLdsUnit = 1, kCsrLds = 2;
+constexpr int kCsrGlobal = 0, kCsrLdsUnit = 1, kCsrLds = 2, kEllUnit = 3;
+constexpr int kEllSlices = kAdjMaxN / 4 / 64;  // slices of 64 quads at the size limit
 
 struct AdjArgs {
     const int64_t* row_ptr;
@@ -53,6 +57,7 @@ struct AdjArgs {
     const float* J;
     int tabN;              // table length in LDS (largest instance, rounded up to 4)
     int64_t max_nnz;       // most stored entries of one instance
+    int64_t max_ell;       // most padded row-image entries of one instance (kEllUnit)
     const int4* inst;      // per instance: first slice, slices, first oscillator, size
     int I, n_total, P;     // instances, oscillators, padded words per replica
     int R, q, steps, C, nseg;
@@ -112,21 +117,29 @@ __device__ __forceinline__ size_t slot_index(const AdjArgs& a, const Ctx& x, int
 // made at kernel start (row offsets relative to the instance, 16-bit local
 // column indices, and either FP32 weights or, with UNIT, the sign of a
 // unit weight in the index's top bit); otherwise the global CSR through L2.
+// ELL_UNIT (unit weights, forward kernel): the step loop reads a padded row
+// image in LDS (gather_quad_ell); the whole-row sums of the loss use the
+// global CSR.
 template <int MODE>
 struct Rows {
+    static constexpr bool kGlobal = MODE == kCsrGlobal || MODE == kEllUnit;
     const AdjArgs* a;
     int off;
     const int32_t* rp;    // LDS row offsets [nb + 1]
     const uint16_t* col;  // LDS column indices
     const float* w;       // LDS weights (MODE == kCsrLds)
+    // ELL_UNIT: the row image and, per slice of the thread's quads, the
+    // padded row length and the slice's offset in the image (wave-uniform)
+    const uint16_t* ell;
+    int ellD[kAdjQPT], ellBase[kAdjQPT];
     __device__ __forceinline__ int64_t begin(int i) const {
-        return MODE == kCsrGlobal ? a->row_ptr[off + i] : (int64_t)rp[i];
+        return kGlobal ? a->row_ptr[off + i] : (int64_t)rp[i];
     }
     __device__ __forceinline__ int64_t end(int i) const {
-        return MODE == kCsrGlobal ? a->row_ptr[off + i + 1] : (int64_t)rp[i + 1];
+        return kGlobal ? a->row_ptr[off + i + 1] : (int64_t)rp[i + 1];
     }
     __device__ __forceinline__ void edge(int64_t e, int& j, float& wt) const {
-        if constexpr (MODE == kCsrGlobal) {
+        if constexpr (kGlobal) {
             j = a->col[e] - off;
             wt = a->J[e];
         } else if constexpr (MODE == kCsrLdsUnit) {
@@ -232,6 +245,49 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
     Dl = D0 + D1;
 }
 
+// Forward sums (A, B of gather) for the four rows of quad k of the thread from
+// the ELL row image: the slice's rows are padded to one length D (a multiple
+// of 4; pads point at the tables' zero entry), entry e of row j of the lane's
+// quad at u16 offset base + ((j D/4 + e/4) 64 + lane) 4 + e % 4, so each
+// 8-byte read brings four consecutive entries of one row and the loop length
+// is the same for the whole wave.  Per row the partial sums take the even and
+// the odd entries in order, exactly as gather does, and a pad adds +-0 to a
+// partial sum that is never -0: the results are the same bits.
+__device__ __forceinline__ void gather_quad_ell(const Rows<kEllUnit>& g, const float4* tab, int k,
+                                                int lane, float (&A)[4], float (&B)[4]) {
+    const int D4 = g.ellD[k] >> 2;
+    const uint2* img = reinterpret_cast<const uint2*>(g.ell + g.ellBase[k]) + lane;
+    float a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) a0[j] = b0[j] = a1[j] = b1[j] = 0.f;
+    for (int gi = 0; gi < D4; ++gi) {
+        uint2 v[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = img[(j * D4 + gi) * 64];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const uint32_t word = t < 2 ? v[j].x : v[j].y;
+                const uint32_t c = (t & 1) ? word >> 16 : word & 0xffffu;
+                const float wt = (c & 0x8000u) ? -1.0f : 1.0f;
+                const float2 p = *reinterpret_cast<const float2*>(tab + (c & 0x7fffu));
+                if (t & 1) {
+                    a1[j] = __builtin_fmaf(wt, p.y, a1[j]);
+                    b1[j] = __builtin_fmaf(wt, p.x, b1[j]);
+                } else {
+                    a0[j] = __builtin_fmaf(wt, p.y, a0[j]);
+                    b0[j] = __builtin_fmaf(wt, p.x, b0[j]);
+                }
+            }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        A[j] = a0[j] + a1[j];
+        B[j] = b0[j] + b1[j];
+    }
+}
+
 // Writes (s, c) of the thread's oscillators into a table.
 __device__ __forceinline__ void put_sc(const Ctx& x, float4* tab, const uint32_t (&u)[kAdjQPT][4]) {
 #pragma unroll
@@ -261,12 +317,19 @@ __device__ __forceinline__ void fwd_step(const AdjArgs& a, const Ctx& x, const R
         if (m >= x.nq) break;
         float z[4];
         normals4((uint32_t)m, t, (uint32_t)x.b, x.k0, x.k1, z);
+        float Aq[4], Bq[4];
+        if constexpr (MODE == kEllUnit) gather_quad_ell(g, tin, k, threadIdx.x & 63, Aq, Bq);
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * m + j;
             if (i >= x.nb) break;
             float A, B, Cl, Dl;
-            gather<false>(g, tin, i, A, B, Cl, Dl);
+            if constexpr (MODE == kEllUnit) {
+                A = Aq[j];
+                B = Bq[j];
+            } else {
+                gather<false>(g, tin, i, A, B, Cl, Dl);
+            }
             const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
             const float coup = __builtin_fmaf(si, A, -(ci * B));
             const float drift = __builtin_fmaf(kc, coup, ks * sin_q<QM>(si, ci, u[k][j], q));
@@ -307,14 +370,72 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
-// Dynamic LDS: two tables of tabN float4, then (CSR in LDS) the instance's
-// row offsets, 16-bit column indices and FP32 weights.  Fills the CSR copy.
+// Dynamic LDS: two tables of tabN + 1 float4 (entry tabN of each stays zero),
+// then (CSR in LDS) the instance's row offsets, 16-bit column indices and FP32
+// weights, or (ELL_UNIT) per-slice lengths and the padded row image.  Fills
+// the row copy; the caller's first barrier publishes it.
 template <int MODE>
 __device__ __forceinline__ Rows<MODE> setup_rows(const AdjArgs& a, const Ctx& x, unsigned char* smem) {
     Rows<MODE> g;
     g.a = &a;
     g.off = x.off;
-    unsigned char* p = smem + (size_t)32 * a.tabN;
+    float4* tabs = reinterpret_cast<float4*>(smem);
+    if (threadIdx.x < 2) tabs[(size_t)threadIdx.x * (a.tabN + 1) + a.tabN] = make_float4(0.f, 0.f, 0.f, 0.f);
+    unsigned char* p = smem + (size_t)32 * (a.tabN + 1);
+    if constexpr (MODE == kEllUnit) {
+        // slice s holds quads 64 s .. 64 s + 63, i.e. the quads of wave
+        // s % 8 for k = s / 8 (thread t owns quad t + k kAdjTB)
+        int* lenD = reinterpret_cast<int*>(p);
+        g.ell = reinterpret_cast<const uint16_t*>(p + 16 * kEllSlices);
+        uint16_t* img = reinterpret_cast<uint16_t*>(p + 16 * kEllSlices);
+        const int lane = threadIdx.x & 63;
+        int deg[kAdjQPT][4];
+        int64_t rb[kAdjQPT][4];
+#pragma unroll
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int m = threadIdx.x + k * kAdjTB;
+            int dmax = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * m + j;
+                rb[k][j] = i < x.nb ? a.row_ptr[x.off + i] : 0;
+                deg[k][j] = i < x.nb ? (int)(a.row_ptr[x.off + i + 1] - rb[k][j]) : 0;
+                dmax = deg[k][j] > dmax ? deg[k][j] : dmax;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const int other = __shfl_xor(dmax, o, 64);
+                dmax = other > dmax ? other : dmax;
+            }
+            const int s = m >> 6;
+            if (lane == 0 && s < kEllSlices) lenD[s] = (dmax + 3) & ~3;
+        }
+        __syncthreads();
+        const int nsl = (x.nq + 63) >> 6;
+#pragma unroll
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int s = (int)((threadIdx.x + k * kAdjTB) >> 6);
+            int base = 0;
+            for (int s2 = 0; s2 < s && s2 < nsl; ++s2) base += 256 * lenD[s2];
+            const int D = s < nsl ? lenD[s] : 0;
+            g.ellD[k] = __builtin_amdgcn_readfirstlane(D);
+            g.ellBase[k] = __builtin_amdgcn_readfirstlane(base);
+            const int m = threadIdx.x + k * kAdjTB;
+            if (m >= x.nq) continue;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                for (int e = 0; e < D; ++e) {
+                    uint16_t v = (uint16_t)a.tabN;  // pad: the zero entry
+                    if (e < deg[k][j]) {
+                        const int64_t ge = rb[k][j] + e;
+                        const uint32_t c = (uint32_t)(a.col[ge] - x.off);
+                        v = (uint16_t)(c | (a.J[ge] < 0.0f ? 0x8000u : 0u));
+                    }
+                    img[base + ((j * (D >> 2) + (e >> 2)) * 64 + lane) * 4 + (e & 3)] = v;
+                }
+        }
+        return g;
+    }
     g.rp = reinterpret_cast<const int32_t*>(p);
     int32_t* rp = reinterpret_cast<int32_t*>(p);
     p += ((size_t)4 * (a.tabN + 1) + 15) & ~(size_t)15;
@@ -349,7 +470,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
     const Ctx x = make_ctx(a);
     const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
     float4* const tabs = reinterpret_cast<float4*>(smem);
-    auto tab = [&](int k) { return tabs + (size_t)k * a.tabN; };
+    auto tab = [&](int k) { return tabs + (size_t)k * (a.tabN + 1); };
     uint32_t u[kAdjQPT][4];
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k)
@@ -406,7 +527,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
     const Ctx x = make_ctx(a);
     const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
     float4* const tabs = reinterpret_cast<float4*>(smem);
-    auto tab = [&](int k) { return tabs + (size_t)k * a.tabN; };
+    auto tab = [&](int k) { return tabs + (size_t)k * (a.tabN + 1); };
     const int q = QM ? QM : a.q;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwg = a.R * a.I;
@@ -519,7 +640,8 @@ __global__ __launch_bounds__(256) void adjoint_reduce_kernel(const float4* gpart
 using AdjFn = void (*)(AdjArgs);
 
 // LDS bytes of the two tables, and of the CSR copy in each mode.
-size_t tab_bytes(int tabN) { return (size_t)32 * tabN; }
+size_t tab_bytes(int tabN) { return (size_t)32 * (tabN + 1); }
+size_t ell_bytes(int64_t entries) { return 16 * kEllSlices + (((size_t)2 * entries + 15) & ~(size_t)15); }
 size_t csr_bytes(int tabN, int64_t nnz, bool weights) {
     size_t b = ((size_t)4 * (tabN + 1) + 15) & ~(size_t)15;
     b += ((size_t)2 * nnz + 15) & ~(size_t)15;
@@ -528,11 +650,27 @@ size_t csr_bytes(int tabN, int64_t nnz, bool weights) {
 }
 constexpr size_t kAdjLdsLimit = 160 * 1024 - 256;  // dynamic LDS next to the static reduction slots
 
-// CSR placement for a problem: in LDS when it fits (unit weights need no
-// weight array), else read from global memory.
-int csr_mode(const Problem* p, int tabN, size_t* lds) {
+// Row placement for a problem: the padded row image in LDS for unit weights
+// when it fits (forward kernel only), else the CSR in LDS (unit weights need
+// no weight array), else the global CSR.  The backward kernel keeps the CSR:
+// its adjoint gathers read 16-byte table entries, and the padded slots cost
+// more there than the shorter dependency chains save (measured).
+// OIM_ADJ_ROWS=csr or =global skips the earlier choices (a switch for
+// comparing the placements; all give the same bits).
+int csr_mode(const Problem* p, int tabN, size_t* lds, bool allow_ell) {
     const size_t t = tab_bytes(tabN);
     const bool small_idx = p->max_inst_n <= 0x7fff;
+    const char* env = getenv("OIM_ADJ_ROWS");
+    const int skip = env && !strcmp(env, "global") ? 2 : env && !strcmp(env, "csr") ? 1 : 0;
+    if (skip >= 2) {
+        *lds = t;
+        return kCsrGlobal;
+    }
+    if (skip < 1 && allow_ell && small_idx && p->unit_weights && p->max_inst_ell > 0 &&
+        t + ell_bytes(p->max_inst_ell) <= kAdjLdsLimit) {
+        *lds = t + ell_bytes(p->max_inst_ell);
+        return kEllUnit;
+    }
     if (small_idx && p->unit_weights && t + csr_bytes(tabN, p->max_inst_nnz, false) <= kAdjLdsLimit) {
         *lds = t + csr_bytes(tabN, p->max_inst_nnz, false);
         return kCsrLdsUnit;
@@ -547,10 +685,13 @@ int csr_mode(const Problem* p, int tabN, size_t* lds) {
 
 AdjFn forward_fn(int q, int mode) {
     const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
-    static const AdjFn f[3][3] = {
-        {adjoint_forward_kernel<0, 0>, adjoint_forward_kernel<0, 1>, adjoint_forward_kernel<0, 2>},
-        {adjoint_forward_kernel<2, 0>, adjoint_forward_kernel<2, 1>, adjoint_forward_kernel<2, 2>},
-        {adjoint_forward_kernel<3, 0>, adjoint_forward_kernel<3, 1>, adjoint_forward_kernel<3, 2>}};
+    static const AdjFn f[3][4] = {
+        {adjoint_forward_kernel<0, 0>, adjoint_forward_kernel<0, 1>, adjoint_forward_kernel<0, 2>,
+         adjoint_forward_kernel<0, 3>},
+        {adjoint_forward_kernel<2, 0>, adjoint_forward_kernel<2, 1>, adjoint_forward_kernel<2, 2>,
+         adjoint_forward_kernel<2, 3>},
+        {adjoint_forward_kernel<3, 0>, adjoint_forward_kernel<3, 1>, adjoint_forward_kernel<3, 2>,
+         adjoint_forward_kernel<3, 3>}};
     return f[qc][mode];
 }
 
@@ -597,6 +738,7 @@ AdjArgs base_args(const Problem* p, const oim_adjoint_cfg* cfg, const float* K, 
     a.dt = cfg->dt;
     a.tabN = (p->max_inst_n + 3) & ~3;
     a.max_nnz = p->max_inst_nnz;
+    a.max_ell = p->max_inst_ell;
     a.K = K;
     a.Ks = Ks;
     a.sigma = sigma;
@@ -621,7 +763,7 @@ int launch_adjoint_forward(Problem* p, const oim_adjoint_cfg* cfg, const float* 
     a.thetaT = thetaT;
     a.loss = loss;
     size_t lds = 0;
-    const int mode = csr_mode(p, a.tabN, &lds);
+    const int mode = csr_mode(p, a.tabN, &lds, true);
     return launch_adj(forward_fn(cfg->q, mode), lds, cfg->R * p->n_inst, stream, a,
                       "adjoint_forward_kernel");
 }
@@ -654,7 +796,7 @@ int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float*
     a.seg = reinterpret_cast<uint32_t*>(w);
     a.gpart = reinterpret_cast<float4*>(w + (seg_bytes + 255) / 256 * 256);
     size_t lds = 0;
-    const int mode = csr_mode(p, a.tabN, &lds);
+    const int mode = csr_mode(p, a.tabN, &lds, false);
     int st = launch_adj(backward_fn(cfg->q, mode), lds, nwg, stream, a, "adjoint_backward_kernel");
     if (st) return st;
     hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((cfg->steps + 255) / 256), dim3(256), 0, stream,

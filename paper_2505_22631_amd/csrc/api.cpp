@@ -136,6 +136,18 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     p->unit_weights = true;
     for (int64_t e = 0; e < nnz && p->unit_weights; ++e)
         if (std::fabs(J[e]) != 1.0f) p->unit_weights = false;
+    p->max_inst_ell = 0;
+    for (int32_t b = 0; b < n_inst; ++b) {
+        const int32_t r0 = n_inst > 1 ? inst_off[b] : 0, r1 = n_inst > 1 ? inst_off[b + 1] : n;
+        int64_t ell = 0;
+        for (int32_t s0 = r0; s0 < r1; s0 += 256) {
+            int64_t dmax = 0;
+            for (int32_t i = s0; i < std::min(r1, s0 + 256); ++i)
+                dmax = std::max<int64_t>(dmax, row_ptr[i + 1] - row_ptr[i]);
+            ell += 256 * ((dmax + 3) & ~int64_t(3));
+        }
+        p->max_inst_ell = std::max(p->max_inst_ell, ell);
+    }
     weight_stats(p, n, row_ptr, col_idx, J);
     SellImage img;
     build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img);

@@ -57,6 +57,8 @@ struct Problem {
     int32_t n_inst = 1;
     int32_t max_inst_n = 0;  // largest instance (oscillators)
     int64_t max_inst_nnz = 0;  // most stored entries of one instance
+    int64_t max_inst_ell = 0;  // most entries of one instance's padded row image (slices of
+                               // 256 rows, each padded to its longest row rounded up to 4)
     bool unit_weights = false; // every |J| is 1
     int4* d_inst = nullptr;
     int32_t* d_order = nullptr;

@@ -276,3 +276,30 @@ def test_adjoint_rows_from_global_memory_match_oracle(oim, orc, dev):
         ok, rel = _close_vec(got, ref, 1e-4)
         print(f"global rows d/d{name}: max rel err {rel:.2e}")
         assert ok, (name, rel)
+
+
+def test_adjoint_row_placements_give_identical_bits(oim, dev, monkeypatch):
+    # a ragged unit-weight batch runs with the padded row image in LDS by
+    # default; the CSR copy in LDS and the global CSR (forced through
+    # OIM_ADJ_ROWS) must give the same loss, final phases and gradients bit
+    # for bit: every placement sums each row in the same order
+    graphs = [synth.gnp_avg_degree(n, 6.0, seed=40 + i) for i, n in enumerate([300, 517, 129])]
+    big, off = synth.block_diagonal(graphs)
+    steps, R, C = 40, 2, 16
+    K, Ks, sg = _schedules(steps)
+    th0 = synth.theta0(R, big.n, seed=9)
+    sd = synth.seeds(R, 21)
+    outs = {}
+    with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, (-big.w).astype(np.float32),
+                                     off) as prob:
+        for mode in ("", "csr", "global"):
+            if mode:
+                monkeypatch.setenv("OIM_ADJ_ROWS", mode)
+            else:
+                monkeypatch.delenv("OIM_ADJ_ROWS", raising=False)
+            outs[mode] = _gpu_adjoint(oim, prob, th0, K, Ks, sg, sd, 3, C)
+    monkeypatch.delenv("OIM_ADJ_ROWS", raising=False)
+    assert np.all(np.isfinite(outs[""][0]))
+    for mode in ("csr", "global"):
+        for a, b in zip(outs[""], outs[mode]):
+            np.testing.assert_array_equal(a, b)
