@@ -153,7 +153,9 @@ def bench_dense(args, n=4096, fp32=False):
     dt = float(np.float32(0.01))
     J = synth.sk_dense(n, seed=3)
     dev = torch.device("cuda:0")
+    t_up = time.perf_counter()
     prob = oim.Problem.from_dense(J)
+    upload_ms = (time.perf_counter() - t_up) * 1e3
     # frozen from a K x Ks x shape sweep on 128 replicas (mean best energy):
     # the Gershgorin bound is loose for SK couplings, so K_max is 32 times it
     wl = dict(q=q, k_mul=32.0, ks_mul=0.03, ks_shape="ramp", periods=0, sigma=0.1)
@@ -211,6 +213,7 @@ def bench_dense(args, n=4096, fp32=False):
                                + " (per run, incl. epilogue)",
                      "run_ms": run_ms, "flops_per_step": flops_step},
         "best_energy_per_spin": e_per_spin,
+        "problem_upload_ms": upload_ms,
     }
     if not args.no_cpu_baseline and n == 4096:
         out["cpu_baseline"] = cpu_baseline_dense(prob, J, th_init, seeds, Kh, Ksh, sgh, q, dt,
@@ -614,7 +617,9 @@ def main():
     dt = float(np.float32(wl["dt"]))
     import synth
     dev = torch.device("cuda:0")
+    t_up = time.perf_counter()
     prob = oim.Problem.from_csr(g.n, g.row_ptr, g.col, (-g.w).astype(np.float32))
+    upload_ms = (time.perf_counter() - t_up) * 1e3
     K, Ks, sg, kmax, ksmax = _schedules(wl, prob.info["max_abs_row_sum"], steps, dt)
     dK, dKs, dsg = (torch.from_numpy(x).to(dev) for x in (K, Ks, sg))
     th_init = torch.from_numpy(synth.theta0(R, g.n, seed=100)).to(dev)
@@ -787,6 +792,7 @@ def main():
         "best_cut_ref_polish": polished,
         "plain": plain,
         "stepwise_hipgraph_loop": stepwise,
+        "problem_upload_ms": upload_ms,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl)
