@@ -81,14 +81,16 @@ def test_dense_matches_sparse_on_same_coupling(oim, orc):
     assert wrapdiff(a, b).max() < 1e-5
 
 
-def test_dense_in_run_readout(oim, orc):
+@pytest.mark.parametrize("prec", ["bf16x3", "fp32"])
+def test_dense_in_run_readout(oim, orc, prec):
     n, R = 160, 4
     J = synth.sk_dense(n, seed=8)
+    flags = oim.OIM_PREC_BF16X3 if prec == "bf16x3" else oim.OIM_PREC_FP32
     with oim.Problem.from_dense(J) as prob:
         K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], 2, 120)
         th0 = synth.theta0(R, n, seed=2)
         th, ro = _run(oim, prob, th0, K, Ks, sg, synth.seeds(R, 3), 2, readout_every=40,
-                      want_best=True)
+                      want_best=True, flags=flags)
     rp, cl, Jv = orc.dense_to_csr(J)
     tr = ro["trace"]
     assert tr.shape == (3, R)
