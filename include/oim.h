@@ -197,7 +197,7 @@ typedef struct {
     int32_t n_tried;                          /* variants timed (<= OIM_TUNE_MAX listed) */
     int32_t chosen_block;                     /* threads per workgroup of the winner */
     int32_t chosen_slices_per_wave;
-    float chosen_ms;                          /* its trial time */
+    float chosen_ms;                          /* its median time in the final round */
     int32_t block[OIM_TUNE_MAX];              /* every variant tried, in order */
     int32_t slices_per_wave[OIM_TUNE_MAX];
     float ms[OIM_TUNE_MAX];                   /* best of two timings, milliseconds */
@@ -205,10 +205,12 @@ typedef struct {
 
 /* Times every launch variant that covers the problem's largest instance on
  * the first trial_steps steps of the given schedules (device arrays of at
- * least trial_steps entries; seeds [R]; theta [R][n] device, read only: the
- * trials run on a scratch copy, without readout) and keeps the fastest for
- * later oim_run calls on p with the same SHIL order class (q = 2, q = 3,
- * other).  cfg gives q, R, dt; its steps must be >= trial_steps >= 1.
+ * least cfg->steps entries; seeds [R]; theta [R][n] device, read only: the
+ * trials run on a scratch copy, without readout), then the four fastest again
+ * three times on min(cfg->steps, 2 trial_steps) steps, and keeps the one with
+ * the smallest median for later oim_run calls on p with the same SHIL order
+ * class (q = 2, q = 3, other).  cfg gives q, R, dt; its steps must be
+ * >= trial_steps >= 1.
  * report may be NULL.  Synchronous (waits for the trials on stream).
  * Allocates and frees a scratch copy of theta.  Errors: OIM_E_ARG,
  * OIM_E_UNSUPPORTED (dense problem, or a replica that does not fit the

@@ -73,7 +73,11 @@ def test_autotune_keeps_a_variant_and_leaves_theta(oim):
     assert torch.equal(th0, before)
     assert len(rep["tried"]) >= 5
     assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in rep["tried"]]
-    assert rep["ms"] == min(ms for _, _, ms in rep["tried"]) > 0
+    # the winner comes from the four fastest of the first round; its reported
+    # time is its median in the final round (trials twice as long)
+    fastest = sorted(rep["tried"], key=lambda t: t[2])[:4]
+    assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in fastest]
+    assert rep["ms"] > 0
     got, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
     np.testing.assert_array_equal(got, ref)
     with pytest.raises(oim.OimError, match="variant"):
