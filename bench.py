@@ -207,8 +207,8 @@ def bench_dense(args, n=4096, fp32=False):
                    "n": n, "replicas": R, "em_steps": steps, "K_max": kmax, "Ks_max": ksmax},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak,
-                     "traffic": (None if fp32 else
-                                 _measured_traffic(DENSE_PROFILE, DENSE_SOURCES)),
+                     "traffic": (_measured_traffic(DENSE_PROFILE, DENSE_SOURCES)
+                                 if n == 4096 and not fp32 else None),
                      "kernel": ("dense_step32_kernel" if fp32 else "dense_step_kernel")
                                + " (per run, incl. epilogue)",
                      "run_ms": run_ms, "flops_per_step": flops_step},
