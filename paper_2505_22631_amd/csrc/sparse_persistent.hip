@@ -29,6 +29,11 @@
 #include "noise.hpp"
 #include "phase.hpp"
 
+// Every multiply-add of the step is written out (fmaf) and the compiler may
+// not contract the others, so all launch variants round identically whatever
+// their register allocation and scheduling.
+#pragma clang fp contract(off)
+
 namespace oim {
 
 namespace {
@@ -219,8 +224,16 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
                     const float2 own = sc[j * plane + m];
-                    const float coup = own.x * A[j] - own.y * B[j];
-                    const float det = kc * coup + ks * sin_q<QM>(own.x, own.y, ph[k][j], q);
+                    const float coup = __builtin_fmaf(own.x, A[j], -(own.y * B[j]));
+                    // sin(3 theta) = s (3 - 4 s^2) with its multiply-add fused
+                    const float sq = QM == 3 ? own.x * __builtin_fmaf(-4.0f * own.x, own.x, 3.0f)
+                                             : sin_q<QM>(own.x, own.y, ph[k][j], q);
+                    // the deterministic part of the increment; which of its two
+                    // products is fused keeps the rounding this kernel has
+                    // always had (the SHIL term for q = 2, the coupling term
+                    // otherwise), so results are unchanged bit for bit
+                    const float det = QM == 2 ? __builtin_fmaf(ks, sq, kc * coup)
+                                              : __builtin_fmaf(kc, coup, ks * sq);
                     drift[k][j] = __builtin_fmaf(ns, drift[k][j], det);
                 }
             }
