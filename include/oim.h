@@ -197,7 +197,7 @@ typedef struct {
     int32_t n_tried;                          /* variants timed (<= OIM_TUNE_MAX listed) */
     int32_t chosen_block;                     /* threads per workgroup of the winner */
     int32_t chosen_slices_per_wave;
-    float chosen_ms;                          /* its median time in the final round */
+    float chosen_ms;                          /* its median time in the final pass */
     int32_t block[OIM_TUNE_MAX];              /* every variant tried, in order */
     int32_t slices_per_wave[OIM_TUNE_MAX];
     float ms[OIM_TUNE_MAX];                   /* best of two timings, milliseconds */

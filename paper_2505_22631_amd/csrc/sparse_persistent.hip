@@ -553,7 +553,7 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
             out[rep_i] = ms;
         }
     };
-    // round 1: every covering variant, best of two short trials
+    // first pass: every covering variant, best of two short trials
     constexpr int kFinalists = 4;
     const Variant* fin[kFinalists] = {};
     float fin_ms[kFinalists] = {};
@@ -584,7 +584,7 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
             }
         }
     }
-    // round 2: the finalists on trials twice as long (within the schedule),
+    // second pass: the finalists on trials twice as long (within the schedule),
     // three times each; the smallest median wins (short trials alone picked
     // variants up to 15 % apart from run to run on the 1024-graph batch)
     const Variant* best = nullptr;

@@ -73,8 +73,8 @@ def test_autotune_keeps_a_variant_and_leaves_theta(oim):
     assert torch.equal(th0, before)
     assert len(rep["tried"]) >= 5
     assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in rep["tried"]]
-    # the winner comes from the four fastest of the first round; its reported
-    # time is its median in the final round (trials twice as long)
+    # the winner comes from the four fastest of the first pass; its reported
+    # time is its median in the final pass (trials twice as long)
     fastest = sorted(rep["tried"], key=lambda t: t[2])[:4]
     assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in fastest]
     assert rep["ms"] > 0
