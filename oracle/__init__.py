@@ -67,6 +67,13 @@ def lib():
         L.orc_h_model.restype = _f64
         L.orc_h_eq6.argtypes = [_i32, _P, _P, _P, _P]
         L.orc_h_eq6.restype = _f64
+        L.orc_run_csr_instance.argtypes = [_i32, _P, _P, _P, _u32, _i32, _i32, _i32, _i64, _f64,
+                                           _P, _P, _P, _P, _P, _i32]
+        L.orc_run_csr_instance.restype = ctypes.c_int
+        L.orc_pairwise_tree.argtypes = [_P, _i64]
+        L.orc_pairwise_tree.restype = _f64
+        L.orc_upper_row_sums.argtypes = [_i32, _P, _P, _P, _i32, _i32, _P, _P, _P]
+        L.orc_upper_row_sums.restype = None
         _lib = L
     return _lib
 
@@ -121,12 +128,16 @@ def _per_replica(fn, theta0, K, Ks, sigma, seeds, **kw):
     return out
 
 
-def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
+def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0,
+            instance=0):
     """Integrate Eq. 5 (Algorithm 1) on a CSR coupling; returns theta [R][n] in FP64.
-    K, Ks, sigma are [steps] (shared) or [R][steps] (one schedule per replica)."""
+    K, Ks, sigma are [steps] (shared) or [R][steps] (one schedule per replica).
+    `instance` = b integrates the graph as instance b of a block-diagonal batch
+    (the noise counter carries b)."""
     if np.ndim(K) == 2:
         return _per_replica(lambda th, **k: run_csr(row_ptr, col, J, th, **k), theta0, K, Ks,
-                            sigma, seeds, q=q, dt=dt, step0=step0, nthreads=nthreads)
+                            sigma, seeds, q=q, dt=dt, step0=step0, nthreads=nthreads,
+                            instance=instance)
     rp = _c(row_ptr, np.int64)
     cl = _c(col, np.int32)
     Jv = _c(J, np.float64)
@@ -137,11 +148,12 @@ def run_csr(row_ptr, col, J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nth
     steps = len(K)
     sd = _c(seeds, np.uint64)
     assert sd.shape == (R,) and rp.shape == (n + 1,)
-    rc = lib().orc_run_csr(n, _ptr(rp), _ptr(cl), _ptr(Jv), int(q), R, steps, int(step0),
-                           float(dt), _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
-                           _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), int(nthreads))
+    rc = lib().orc_run_csr_instance(n, _ptr(rp), _ptr(cl), _ptr(Jv), int(instance), int(q), R,
+                                    steps, int(step0), float(dt), _ptr(_sched(K, steps)),
+                                    _ptr(_sched(Ks, steps)), _ptr(_sched(sigma, steps)),
+                                    _ptr(sd), _ptr(th), int(nthreads))
     if rc != 0:
-        raise ValueError("orc_run_csr rejected its arguments")
+        raise ValueError("orc_run_csr_instance rejected its arguments")
     return th
 
 
@@ -287,3 +299,53 @@ def h_eq6(row_ptr, col, J, theta) -> float:
     Jv = _c(J, np.float64)
     th = _c(theta, np.float64)
     return float(lib().orc_h_eq6(len(rp) - 1, _ptr(rp), _ptr(cl), _ptr(Jv), _ptr(th)))
+
+
+# ------------------------------------------------- fixed-order readouts ----
+# The order every GPU readout of a real-weighted sum follows: per row i, the
+# terms of j > i in ascending column order, summed in FP64 from +0; then the
+# pairwise tree over the rows (zero-padded to a power of two, adjacent pairs
+# first).  Integer weights give the same value in any order.
+def pairwise_tree(values) -> float:
+    v = _c(values, np.float64)
+    return float(lib().orc_pairwise_tree(_ptr(v), v.size))
+
+
+def upper_row_sums(row_ptr, col, J, kind, *, q=2, colour=None, theta=None) -> np.ndarray:
+    """Per-row FP64 sums over j > i: kind 'cut' (-J when colours differ),
+    'model' (Eq. 1 for q = 2, Eq. 2 for q >= 3) or 'eq6' (-J cos(th_i - th_j))."""
+    rp, cl = _c(row_ptr, np.int64), _c(col, np.int32)
+    Jv = _c(J, np.float64)
+    n = len(rp) - 1
+    k = {"cut": 0, "model": 1, "eq6": 2}[kind]
+    co = _c(colour if colour is not None else np.zeros(n), np.int8)
+    th = _c(theta if theta is not None else np.zeros(n), np.float64)
+    assert co.shape == (n,) and th.shape == (n,)
+    out = np.zeros(n, np.float64)
+    lib().orc_upper_row_sums(n, _ptr(rp), _ptr(cl), _ptr(Jv), k, int(q), _ptr(co), _ptr(th),
+                             _ptr(out))
+    return out
+
+
+def _fixed(row_ptr, col, J, kind, inst_off, **kw):
+    rows = upper_row_sums(row_ptr, col, J, kind, **kw)
+    if inst_off is None:
+        return pairwise_tree(rows)
+    return np.array([pairwise_tree(rows[inst_off[b]:inst_off[b + 1]])
+                     for b in range(len(inst_off) - 1)])
+
+
+def cut_fixed(row_ptr, col, J, colour, inst_off=None):
+    """Max-cut value sum_{i<j} (-J_ij) [k_i != k_j] in the fixed FP64 order
+    (per instance when inst_off is given)."""
+    return _fixed(row_ptr, col, J, "cut", inst_off, colour=colour)
+
+
+def h_model_fixed(row_ptr, col, J, q, colour, inst_off=None):
+    """Eq. 1 (q = 2) or Eq. 2 (q >= 3) in the fixed FP64 order."""
+    return _fixed(row_ptr, col, J, "model", inst_off, q=q, colour=colour)
+
+
+def h_eq6_fixed(row_ptr, col, J, theta, inst_off=None):
+    """Eq. 6 with w = -J at continuous phases, in the fixed FP64 order."""
+    return _fixed(row_ptr, col, J, "eq6", inst_off, theta=theta)

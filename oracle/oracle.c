@@ -107,55 +107,102 @@ static double wrap_2pi(double th) {
 /* Integrators.  theta is [R][n], FP64, in/out.  J is the Ising coupling.    */
 /* Returns 0, or -1 on a bad argument.                                       */
 /* ------------------------------------------------------------------------ */
+/* The derivative loop of Algorithm 1 for oscillators i0 .. i1-1: each
+ * coupling sum c_i = sum_{j != i} J_ij sin(th_i - th_j) from the phases of
+ * step t, in row order. */
+static void coupling_rows(int32_t i0, int32_t i1, int32_t n, const int64_t* row_ptr,
+                          const int32_t* col, const double* Jv, const double* Jdense,
+                          const double* th, double* coup) {
+    for (int32_t i = i0; i < i1; ++i) {
+        double acc = 0.0;
+        if (Jdense) {
+            for (int32_t j = 0; j < n; ++j)
+                if (j != i) acc += Jdense[(int64_t)i * n + j] * sin(th[i] - th[j]);
+        } else {
+            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
+                acc += Jv[e] * sin(th[i] - th[col[e]]);
+        }
+        coup[i] = acc;
+    }
+}
+
+/* The update loop of Algorithm 1 for oscillators i0 .. i1-1: forward Euler
+ * with the SHIL term and the noise kick, then the wrap into one period. */
+static void update_rows(int32_t i0, int32_t i1, int32_t q, double dt, double Kt, double Kst,
+                        double sigt, uint64_t seed, uint32_t t, const uint32_t* inst_of,
+                        const uint32_t* local, const double* coup, double* th) {
+    const double sq = sqrt(dt);
+    for (int32_t i = i0; i < i1; ++i) {
+        const double f = -Kt * coup[i] - Kst * sin((double)q * th[i]);
+        const double xi = orc_normal_b(seed, local[i], t, inst_of[i]);
+        th[i] = wrap_2pi(th[i] + dt * f + sigt * sq * xi);
+    }
+}
+
 static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* Jv,
                       const double* Jdense, int32_t q, int32_t R, int32_t steps, int64_t step0,
                       double dt, const double* K, const double* Ks, const double* sigma,
                       const uint64_t* seeds, double* theta, int32_t nthreads, int32_t n_inst,
-                      const int32_t* inst_off) {
+                      const int32_t* inst_off, uint32_t inst_base) {
     if (n < 1 || R < 1 || steps < 0 || q < 2 || !(dt > 0.0)) return -1;
     /* instance of every oscillator and its index within the instance */
     uint32_t* inst_of = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
     uint32_t* local = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)n);
     if (!inst_of || !local) { free(inst_of); free(local); return -1; }
-    for (int32_t i = 0; i < n; ++i) { inst_of[i] = 0; local[i] = (uint32_t)i; }
+    for (int32_t i = 0; i < n; ++i) { inst_of[i] = inst_base; local[i] = (uint32_t)i; }
     if (inst_off && n_inst > 1) {
         for (int32_t b = 0; b < n_inst; ++b)
             for (int32_t i = inst_off[b]; i < inst_off[b + 1]; ++i) {
-                inst_of[i] = (uint32_t)b;
+                inst_of[i] = inst_base + (uint32_t)b;
                 local[i] = (uint32_t)(i - inst_off[b]);
             }
     }
+    int threads = 1;
 #ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
+    threads = nthreads > 0 ? nthreads : omp_get_max_threads();
 #else
     (void)nthreads;
 #endif
     int bad = 0;
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int32_t r = 0; r < R; ++r) {
-        double* th = theta + (int64_t)r * n;
-        double* coup = (double*)malloc(sizeof(double) * (size_t)n);
-        if (!coup) { bad = 1; continue; }
-        for (int32_t s = 0; s < steps; ++s) {
-            const uint32_t t = (uint32_t)(step0 + s);
-            /* derivative loop: every coupling sum from the phases of step t */
-            for (int32_t i = 0; i < n; ++i) {
-                double acc = 0.0;
-                if (Jdense) {
-                    for (int32_t j = 0; j < n; ++j)
-                        if (j != i) acc += Jdense[(int64_t)i * n + j] * sin(th[i] - th[j]);
-                } else {
-                    for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e)
-                        acc += Jv[e] * sin(th[i] - th[col[e]]);
-                }
-                coup[i] = acc;
+    if (R >= threads || threads == 1) {
+        /* replicas are independent: one replica per thread at a time */
+#pragma omp parallel for schedule(dynamic, 1) num_threads(threads)
+        for (int32_t r = 0; r < R; ++r) {
+            double* th = theta + (int64_t)r * n;
+            double* coup = (double*)malloc(sizeof(double) * (size_t)n);
+            if (!coup) { bad = 1; continue; }
+            for (int32_t s = 0; s < steps; ++s) {
+                coupling_rows(0, n, n, row_ptr, col, Jv, Jdense, th, coup);
+                update_rows(0, n, q, dt, K[s], Ks[s], sigma[s], seeds[r], (uint32_t)(step0 + s),
+                            inst_of, local, coup, th);
             }
-            /* update loop: forward Euler + SHIL + noise, then wrap */
-            const double sq = sqrt(dt);
-            for (int32_t i = 0; i < n; ++i) {
-                const double f = -K[s] * coup[i] - Ks[s] * sin((double)q * th[i]);
-                const double xi = orc_normal_b(seeds[r], local[i], t, inst_of[i]);
-                th[i] = wrap_2pi(th[i] + dt * f + sigma[s] * sq * xi);
+            free(coup);
+        }
+    } else {
+        /* fewer replicas than threads: the oscillators of one replica are
+         * split into contiguous ranges, one per thread, with a barrier
+         * between the two loops of every step; every oscillator's arithmetic
+         * is the same as in the serial loops */
+        double* coup = (double*)malloc(sizeof(double) * (size_t)n);
+        if (!coup) bad = 1;
+        for (int32_t r = 0; r < R && !bad; ++r) {
+            double* th = theta + (int64_t)r * n;
+#pragma omp parallel num_threads(threads)
+            {
+                int me = 0, nt = 1;
+#ifdef _OPENMP
+                me = omp_get_thread_num();
+                nt = omp_get_num_threads();
+#endif
+                const int32_t i0 = (int32_t)((int64_t)n * me / nt);
+                const int32_t i1 = (int32_t)((int64_t)n * (me + 1) / nt);
+                for (int32_t s = 0; s < steps; ++s) {
+                    coupling_rows(i0, i1, n, row_ptr, col, Jv, Jdense, th, coup);
+#pragma omp barrier
+                    update_rows(i0, i1, q, dt, K[s], Ks[s], sigma[s], seeds[r],
+                                (uint32_t)(step0 + s), inst_of, local, coup, th);
+#pragma omp barrier
+                }
             }
         }
         free(coup);
@@ -170,7 +217,18 @@ int orc_run_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const dou
                 const double* Ks, const double* sigma, const uint64_t* seeds, double* theta,
                 int32_t nthreads) {
     return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
-                      theta, nthreads, 1, NULL);
+                      theta, nthreads, 1, NULL, 0u);
+}
+
+/* A single graph integrated as instance `b` of a block-diagonal batch: the
+ * same trajectory that instance b of the batch follows (its noise counter
+ * carries b). */
+int orc_run_csr_instance(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                         uint32_t b, int32_t q, int32_t R, int32_t steps, int64_t step0,
+                         double dt, const double* K, const double* Ks, const double* sigma,
+                         const uint64_t* seeds, double* theta, int32_t nthreads) {
+    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+                      theta, nthreads, 1, NULL, b);
 }
 
 /* Block-diagonal batch: instance b holds oscillators inst_off[b] .. inst_off[b+1]-1
@@ -182,14 +240,14 @@ int orc_run_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col, co
                        const double* sigma, const uint64_t* seeds, double* theta,
                        int32_t nthreads) {
     return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
-                      theta, nthreads, n_inst, inst_off);
+                      theta, nthreads, n_inst, inst_off, 0u);
 }
 
 int orc_run_dense(int32_t n, const double* J, int32_t q, int32_t R, int32_t steps, int64_t step0,
                   double dt, const double* K, const double* Ks, const double* sigma,
                   const uint64_t* seeds, double* theta, int32_t nthreads) {
     return run_common(n, NULL, NULL, NULL, J, q, R, steps, step0, dt, K, Ks, sigma, seeds, theta,
-                      nthreads, 1, NULL);
+                      nthreads, 1, NULL, 0u);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -276,6 +334,58 @@ double orc_h_eq6(int32_t n, const int64_t* row_ptr, const int32_t* col, const do
     return h;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Readouts in one fixed FP64 order (the reading this build takes of "cut    */
+/* values bit-exact from identical spins" for real weights; integer weights  */
+/* give the same value in any order).  Each row i sums its terms over the    */
+/* upper triangle j > i in ascending column order, starting from +0.  The    */
+/* row sums are then combined by the pairwise tree over rows: the rows are   */
+/* padded with zeros to a power of two and adjacent pairs are added level    */
+/* by level, the lower-indexed partial sum on the left.                      */
+/* ------------------------------------------------------------------------ */
+double orc_pairwise_tree(const double* v, int64_t count) {
+    if (count <= 0) return 0.0;
+    int64_t P = 1;
+    while (P < count) P <<= 1;
+    double* w = (double*)malloc(sizeof(double) * (size_t)P);
+    if (!w) return NAN;
+    for (int64_t k = 0; k < P; ++k) w[k] = k < count ? v[k] : 0.0;
+    for (int64_t len = P; len > 1; len >>= 1)
+        for (int64_t k = 0; k < len / 2; ++k) w[k] = w[2 * k] + w[2 * k + 1];
+    const double s = w[0];
+    free(w);
+    return s;
+}
+
+/* Row sums of one readout's terms over j > i (CSR order is ascending j).
+ * kind 0, cut (Sec. II-C, w = -J):  -J_ij when the colours differ, else 0
+ * kind 1, Eq. 1 (q = 2):            -J_ij s_i s_j with s = 1 - 2k
+ *         Eq. 2 (q >= 3):           -J_ij when the colours are equal, else 0
+ * kind 2, Eq. 6 (w = -J):           -J_ij cos(theta_i - theta_j)          */
+void orc_upper_row_sums(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* J,
+                        int32_t kind, int32_t q, const int8_t* colour, const double* theta,
+                        double* out) {
+    for (int32_t i = 0; i < n; ++i) {
+        double acc = 0.0;
+        for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+            const int32_t j = col[e];
+            if (j <= i) continue;
+            double term;
+            if (kind == 0) {
+                term = colour[i] != colour[j] ? -J[e] : 0.0;
+            } else if (kind == 1) {
+                if (q == 2) term = colour[i] == colour[j] ? -J[e] : J[e];
+                else term = colour[i] == colour[j] ? -J[e] : 0.0;
+            } else {
+                const double c = cos(theta[i] - theta[j]);
+                term = -J[e] * c;
+            }
+            acc += term;
+        }
+        out[i] = acc;
+    }
+}
+
 int orc_abi_version(void) { return 1; }
 
 /* ------------------------------------------------------------------------ */
@@ -329,11 +439,11 @@ int orc_adjoint_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col
         /* forward, keeping every state */
         memcpy(traj, theta0 + (size_t)r * N, sizeof(double) * N);
         if (run_common(n, row_ptr, col, J, NULL, q, 1, 0, step0, dt, K, Ks, sigma, seeds + r,
-                       traj, 1, n_inst, inst_off) != 0) { total = NAN; break; }
+                       traj, 1, n_inst, inst_off, 0u) != 0) { total = NAN; break; }
         for (int32_t s = 0; s < steps; ++s) {
             memcpy(traj + N * (s + 1), traj + N * s, sizeof(double) * N);
             if (run_common(n, row_ptr, col, J, NULL, q, 1, 1, step0 + s, dt, K + s, Ks + s,
-                           sigma + s, seeds + r, traj + N * (s + 1), 1, n_inst, inst_off) != 0) {
+                           sigma + s, seeds + r, traj + N * (s + 1), 1, n_inst, inst_off, 0u) != 0) {
                 total = NAN;
                 break;
             }

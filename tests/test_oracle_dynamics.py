@@ -217,6 +217,39 @@ def test_block_batch_instances(orc):
     assert orc.normal(5, 3, 7, 1) != orc.normal(5, 3, 7, 0)
 
 
+def test_single_instance_is_its_block(orc):
+    # a graph integrated alone as instance b follows instance b of the batch
+    gs = [synth.random_small(n, 0.3, seed=n, weights="pm1") for n in (9, 14, 6)]
+    big, off = _concat(gs)
+    steps = 20
+    kw = dict(q=3, dt=0.01, K=synth.ramp(0.1, 1.0, steps), Ks=synth.ramp(0, 2.0, steps),
+              sigma=synth.const(0.2, steps), seeds=synth.seeds(2, 9), step0=11)
+    th0 = synth.theta0(2, big.n, seed=4)
+    out = orc.run_csr_blocks(big.row_ptr, big.col, -big.w, off, th0, **kw)
+    for b, g in enumerate(gs):
+        alone = orc.run_csr(g.row_ptr, g.col, -g.w, th0[:, off[b]:off[b + 1]], instance=b, **kw)
+        np.testing.assert_array_equal(out[:, off[b]:off[b + 1]], alone)
+
+
+def test_threads_over_rows_give_the_same_bits(orc):
+    # one replica with its rows shared among threads, and the dense loop,
+    # equal the single-thread run bit for bit
+    g = synth.gnp_avg_degree(300, 8.0, seed=3, signed=True)
+    steps = 30
+    kw = dict(q=2, dt=0.01, K=synth.ramp(0.5, 3.0, steps), Ks=synth.ramp(0, 5.0, steps),
+              sigma=synth.const(0.1, steps), seeds=synth.seeds(1, 2))
+    th0 = synth.theta0(1, g.n, seed=5)
+    one = orc.run_csr(g.row_ptr, g.col, -g.w, th0, nthreads=1, **kw)
+    for t in (2, 3, 8):
+        np.testing.assert_array_equal(orc.run_csr(g.row_ptr, g.col, -g.w, th0, nthreads=t, **kw),
+                                      one)
+    Jd = synth.sk_dense(64, seed=1).astype(np.float64)
+    th1 = synth.theta0(2, 64, seed=6)
+    kw2 = dict(kw, seeds=synth.seeds(2, 2))
+    d1 = orc.run_dense(Jd, th1, nthreads=1, **kw2)
+    np.testing.assert_array_equal(orc.run_dense(Jd, th1, nthreads=5, **kw2), d1)
+
+
 @pytest.mark.parametrize("q", [2, 3])
 def test_adjoint_matches_finite_differences(orc, q):
     # The FP64 adjoint's gradient of the relaxed cut against central
