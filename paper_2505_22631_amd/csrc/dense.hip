@@ -26,6 +26,7 @@
 #include "internal.hpp"
 #include "noise.hpp"
 #include "phase.hpp"
+#include "tree.hpp"
 
 namespace oim {
 
@@ -596,29 +597,38 @@ __global__ __launch_bounds__(256) void dense_split_kernel(const float* J, unsign
 }
 
 // Thresholded energy per replica from the phase words (in-run readout):
-// one workgroup per replica, rows strided over threads, FP64 sums in a
-// fixed order.  H = Eq. 1 (q = 2) or Eq. 2 (q >= 3).
+// one workgroup per replica, H = Eq. 1 (q = 2) or Eq. 2 (q >= 3) in the
+// library's fixed FP64 order: thread t owns row 256 b + t of block b and
+// sums its terms over j > i in column order; a block's rows are folded by
+// the pairwise tree (lanes by the xor butterfly, partner distance 1, ..., 32,
+// then the four waves), and the blocks by the same tree, in order, in
+// thread 0.
 __global__ __launch_bounds__(256) void dense_readout_kernel(const float* J, const uint32_t* U,
                                                             int n, int np, int q, double* Hout) {
     __shared__ double red[4];
+    __shared__ double stack[TreeAcc::kLevels];
     const int r = blockIdx.x;
     const uint32_t* ur = U + (size_t)r * np;
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-        const int ci = nearest_state(ur[i], q);
-        const float* row = J + (size_t)i * n;
+    TreeAcc tree(stack);
+    for (int i0 = 0; i0 < n; i0 += 256) {
+        const int i = i0 + (int)threadIdx.x;
         double part = 0.0;
-        for (int j = i + 1; j < n; ++j) {
-            const int cj = nearest_state(ur[j], q);
-            const double w = (double)row[j];
-            part += (q == 2) ? (ci == cj ? w : -w) : (ci == cj ? w : 0.0);
+        if (i < n) {
+            const int ci = nearest_state(ur[i], q);
+            const float* row = J + (size_t)i * n;
+            for (int j = i + 1; j < n; ++j) {
+                const int cj = nearest_state(ur[j], q);
+                const double w = (double)row[j];
+                part += (q == 2) ? (ci == cj ? w : -w) : (ci == cj ? w : 0.0);
+            }
         }
-        acc += part;
+        for (int o = 1; o < 64; o <<= 1) part += __shfl_xor(part, o, 64);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) tree.push((red[0] + red[1]) + (red[2] + red[3]));
+        __syncthreads();
     }
-    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) Hout[r] = -(red[0] + red[1] + red[2] + red[3]);
+    if (threadIdx.x == 0) Hout[r] = -tree.finish();
 }
 
 // Trace / best-so-far bookkeeping after a readout (one thread per replica).

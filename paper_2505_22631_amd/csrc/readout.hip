@@ -8,12 +8,22 @@
 //              w = -J at the continuous phases, FP64
 //
 // One workgroup per replica walks the upper triangle of the coupling (CSR
-// rows, or the dense matrix), each thread a strided set of rows, and the
-// partial sums are combined in a fixed order (wave butterfly, then waves in
-// order), so results are reproducible run to run.  Integer weights are
-// accumulated in int64 and are exact.
+// rows, or the dense matrix).  Every FP64 sum follows one fixed order, the
+// same in every readout of the library: each row i sums its terms over
+// j > i in ascending column order, from +0, and the row sums are combined by
+// the pairwise tree over rows (zero-padded to a power of two, adjacent pairs
+// first, the lower rows on the left).  Here a thread owns one row of a block
+// of 256; the block's tree runs over lanes (xor butterfly, partner distance
+// 1, 2, ..., 32) and then over the four waves; the blocks are combined by
+// the same tree, built incrementally in the order the blocks complete
+// (tree_push / tree_finish).  Integer weights are accumulated in int64 and
+// are exact.
 #include "internal.hpp"
 #include "phase.hpp"
+#include "tree.hpp"
+
+// products and sums of the readouts are rounded one by one, as written
+#pragma clang fp contract(off)
 
 namespace oim {
 
@@ -21,16 +31,18 @@ namespace {
 
 constexpr int kTB = 256;
 
+// Sum of a 256-thread block's values, one per row of the block, by the
+// pairwise tree over the rows (thread t = row t); valid in thread 0.
 template <typename T>
-__device__ T block_sum(T v, T* scratch) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+__device__ T block_tree(T v, T* scratch) {
+    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     if (lane == 0) scratch[wave] = v;
     __syncthreads();
     T tot = 0;
-    if (threadIdx.x == 0)
-        for (int w = 0; w < kTB / 64; ++w) tot += scratch[w];
-    return tot;  // valid in thread 0
+    if (threadIdx.x == 0) tot = (scratch[0] + scratch[1]) + (scratch[2] + scratch[3]);
+    __syncthreads();
+    return tot;
 }
 
 __global__ __launch_bounds__(256) void round_kernel(int64_t count, const float* theta, int q,
@@ -64,7 +76,9 @@ __global__ __launch_bounds__(256) void phase_convert_kernel(int64_t count, const
     }
 }
 
-// mode 0: cut (int64 + f64), 1: conflicts, 2: energies
+// mode 0: cut (int64 + f64), 1: conflicts, 2: energies.  Thread t of the
+// workgroup owns row 256 b + t of block b; the block sums are combined in
+// thread 0 by the pairwise tree over blocks.
 template <int MODE, bool DENSE>
 __global__ __launch_bounds__(kTB) void pair_sum_kernel(
     int n, const int64_t* __restrict__ row_ptr, const int32_t* __restrict__ col,
@@ -72,54 +86,66 @@ __global__ __launch_bounds__(kTB) void pair_sum_kernel(
     const float* __restrict__ theta, int q, int64_t* out_i64, double* out_f64a, double* out_f64b) {
     __shared__ int64_t si[kTB / 64];
     __shared__ double sd[kTB / 64];
+    __shared__ double stack[2][TreeAcc::kLevels];
     const int r = blockIdx.x;
     const int8_t* k = colour ? colour + (int64_t)r * n : nullptr;
     const float* th = theta ? theta + (int64_t)r * n : nullptr;
-    int64_t acc_i = 0;
-    double acc_a = 0.0, acc_b = 0.0;
-    for (int i = threadIdx.x; i < n; i += kTB) {
-        const int ki = k ? k[i] : 0;
-        const double ti = th ? (double)th[i] : 0.0;
-        auto visit = [&](int j, float w) {
-            if (MODE == 0) {
-                if (ki != k[j]) {
-                    acc_i += (int64_t)(-w);
-                    acc_a += -(double)w;
+    int64_t tot_i = 0;
+    TreeAcc tree_a(stack[0]), tree_b(stack[1]);
+    for (int i0 = 0; i0 < n; i0 += kTB) {
+        const int i = i0 + (int)threadIdx.x;
+        int64_t acc_i = 0;
+        double acc_a = 0.0, acc_b = 0.0;
+        if (i < n) {
+            const int ki = k ? k[i] : 0;
+            const double ti = th ? (double)th[i] : 0.0;
+            auto visit = [&](int j, float w) {
+                if (MODE == 0) {
+                    if (ki != k[j]) {
+                        acc_i += (int64_t)(-w);
+                        acc_a += -(double)w;
+                    }
+                } else if (MODE == 1) {
+                    if (w != 0.0f && ki == k[j]) acc_i += 1;
+                } else {
+                    if (k) {
+                        if (q == 2) acc_a += (ki == k[j]) ? -(double)w : (double)w;
+                        else if (ki == k[j]) acc_a += -(double)w;
+                    }
+                    if (th) {
+                        const double c = cos(ti - (double)th[j]);
+                        const double term = -(double)w * c;
+                        acc_b += term;
+                    }
                 }
-            } else if (MODE == 1) {
-                if (w != 0.0f && ki == k[j]) acc_i += 1;
+            };
+            if (DENSE) {
+                const float* rowJ = Jd + (int64_t)i * n;
+                for (int j = i + 1; j < n; ++j) visit(j, rowJ[j]);
             } else {
-                if (k) {
-                    if (q == 2) acc_a += (ki == k[j]) ? -(double)w : (double)w;
-                    else if (ki == k[j]) acc_a += -(double)w;
+                for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
+                    const int j = col[e];
+                    if (j > i) visit(j, J[e]);
                 }
-                if (th) acc_b += -(double)w * cos(ti - (double)th[j]);
-            }
-        };
-        if (DENSE) {
-            const float* rowJ = Jd + (int64_t)i * n;
-            for (int j = i + 1; j < n; ++j) visit(j, rowJ[j]);
-        } else {
-            for (int64_t e = row_ptr[i]; e < row_ptr[i + 1]; ++e) {
-                const int j = col[e];
-                if (j > i) visit(j, J[e]);
             }
         }
+        if (MODE == 0 || MODE == 1) {
+            const int64_t bi = block_tree<int64_t>(acc_i, si);
+            if (threadIdx.x == 0) tot_i += bi;
+        }
+        if (MODE == 0 || MODE == 2) {
+            const double ba = block_tree<double>(acc_a, sd);
+            if (threadIdx.x == 0) tree_a.push(ba);
+        }
+        if (MODE == 2) {
+            const double bb = block_tree<double>(acc_b, sd);
+            if (threadIdx.x == 0) tree_b.push(bb);
+        }
     }
-    if (MODE == 0 || MODE == 1) {
-        const int64_t ti = block_sum<int64_t>(acc_i, si);
-        __syncthreads();
-        if (threadIdx.x == 0 && out_i64) out_i64[r] = ti;
-    }
-    if (MODE == 0 || MODE == 2) {
-        const double ta = block_sum<double>(acc_a, sd);
-        __syncthreads();
-        if (threadIdx.x == 0 && out_f64a) out_f64a[r] = ta;
-    }
-    if (MODE == 2) {
-        const double tb = block_sum<double>(acc_b, sd);
-        __syncthreads();
-        if (threadIdx.x == 0 && out_f64b) out_f64b[r] = tb;
+    if (threadIdx.x == 0) {
+        if ((MODE == 0 || MODE == 1) && out_i64) out_i64[r] = tot_i;
+        if ((MODE == 0 || MODE == 2) && out_f64a) out_f64a[r] = tree_a.finish();
+        if (MODE == 2 && out_f64b) out_f64b[r] = tree_b.finish();
     }
 }
 

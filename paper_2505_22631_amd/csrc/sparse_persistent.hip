@@ -28,6 +28,7 @@
 #include "internal.hpp"
 #include "noise.hpp"
 #include "phase.hpp"
+#include "tree.hpp"
 
 // Every multiply-add of the step is written out (fmaf) and the compiler may
 // not contract the others, so all launch variants round identically whatever
@@ -65,6 +66,16 @@ struct PersistArgs {
     int32_t sched_stride;  // 0: one schedule for all replicas; steps: [R][steps]
 };
 
+// Tree levels of the in-run readout's sum over slices (2^8 slices at most).
+constexpr int kSliceTreeLevels = 8;
+
+// Index within the instance of the oscillator at LDS slot `slot`
+// (slot = (i % 4) * plane + i / 4).
+__device__ __forceinline__ int slot_index(int slot, int plane) {
+    const int p = (slot >= plane) + (slot >= 2 * plane) + (slot >= 3 * plane);
+    return 4 * (slot - p * plane) + p;
+}
+
 __device__ __forceinline__ int4 load_pair(__amdgpu_buffer_rsrc_t rsrc, int voff, int soff) {
     return __builtin_bit_cast(int4, __builtin_amdgcn_raw_buffer_load_b128(rsrc, voff, soff, 0));
 }
@@ -90,7 +101,8 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     float2* sc = reinterpret_cast<float2*>(smem);                   // [4 * plane]
     unsigned char* col8 = smem + (size_t)8 * 4 * plane;            // [4 * plane] (readout)
     double* red = reinterpret_cast<double*>(col8 + ((4 * plane + 15) & ~15));  // [W]
-    int* flag = reinterpret_cast<int*>(red + TB / 64);
+    double* tstack = red + TB / 64;                                             // tree levels
+    int* flag = reinterpret_cast<int*>(tstack + kSliceTreeLevels);
 
     constexpr int W = TB / 64;
     const int lane = threadIdx.x & 63;
@@ -272,39 +284,52 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 }
             }
             __syncthreads();
-            double acc = 0.0;
+            // Eq. 1 / Eq. 2 in the library's fixed FP64 order: each row sums
+            // its terms over j > i in column order (the ELL row is the CSR row,
+            // its padding adds zeros); a lane folds its quad's rows as
+            // (r0 + r1) + (r2 + r3) and the lanes by the xor butterfly
+            // (partner distance 1, 2, ..., 32), which is the pairwise tree
+            // over the slice's 256 rows; thread 0 folds the slices, in order,
+            // into the tree over slices, one round of W slices at a time.
+            TreeAccN<kSliceTreeLevels> tree(tstack);
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
+                if (k * W >= S) break;  // uniform over the workgroup
                 const int slice = wave + k * W;
                 if (slice < S) {
                     const int m = slice * 64 + lane;
                     const int D2 = sdeg[k] >> 1;
-                    // padding rows hold only J = 0 entries and add nothing
+                    double rs[4];
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int ci = col8[j * plane + m];
+                        const int own = 4 * m + j;
                         double row = 0.0;
                         for (int e2 = 0; e2 < D2; ++e2) {
                             const int4 v = load_pair(rsrc, voff, (sbase[k] + j * D2 + e2) * 1024);
                             const int c0 = col8[v.x >> 3], c1 = col8[v.z >> 3];
                             const float w0 = __int_as_float(v.y), w1 = __int_as_float(v.w);
+                            // upper triangle only: the neighbour's index from its slot
+                            const bool up0 = slot_index(v.x >> 3, plane) > own;
+                            const bool up1 = slot_index(v.z >> 3, plane) > own;
                             const float t0 = (q == 2) ? (ci == c0 ? w0 : -w0) : (ci == c0 ? w0 : 0.f);
                             const float t1 = (q == 2) ? (ci == c1 ? w1 : -w1) : (ci == c1 ? w1 : 0.f);
-                            row += (double)t0;
-                            row += (double)t1;
+                            row += up0 ? (double)t0 : 0.0;
+                            row += up1 ? (double)t1 : 0.0;
                         }
-                        acc += row;
+                        rs[j] = row;
                     }
+                    double v = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+                    for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+                    if (lane == 0) red[wave] = v;
                 }
+                __syncthreads();
+                if (threadIdx.x == 0)
+                    for (int w = 0; w < W && k * W + w < S; ++w) tree.push(red[w]);
+                __syncthreads();
             }
-            // workgroup reduction (fixed order: lanes by xor butterfly, then waves)
-            for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-            if (lane == 0) red[wave] = acc;
-            __syncthreads();
             if (threadIdx.x == 0) {
-                double tot = 0.0;
-                for (int w = 0; w < W; ++w) tot += red[w];
-                const double H = -0.5 * tot;
+                const double H = -tree.finish();
                 const int kread = (s + a.M) / a.M - 1;
                 if (a.trace) a.trace[(int64_t)kread * a.R * a.I + out_id] = H;
                 int improved = 0;
@@ -387,7 +412,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 size_t lds_bytes(int plane, int tb) {
     size_t b = (size_t)8 * 4 * plane;                 // (sin, cos) table
     b += ((size_t)4 * plane + 15) & ~(size_t)15;      // colours for readout
-    b += sizeof(double) * (tb / 64) + 16;             // reduction scratch + flag
+    b += sizeof(double) * (tb / 64 + kSliceTreeLevels) + 16;  // reduction, tree levels, flag
     return b;
 }
 

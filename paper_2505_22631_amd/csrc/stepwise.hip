@@ -24,6 +24,7 @@
 #include "internal.hpp"
 #include "noise.hpp"
 #include "phase.hpp"
+#include "tree.hpp"
 
 namespace oim {
 
@@ -171,34 +172,38 @@ struct ReadArgs {
     int k, steps, n, Rp, q;
 };
 
-// Partial sums of sum_i sum_{j in N(i)} J_ij term(k_i, k_j) per block of quads
-// and replica (term = s_i s_j for q = 2, delta(k_i, k_j) for q >= 3).
+// Partial sums of sum_{i<j} J_ij term(k_i, k_j) per block of 16 rows (four
+// quads, one per wave) and replica (term = s_i s_j for q = 2, delta(k_i, k_j)
+// for q >= 3), in the library's fixed FP64 order: each row over j > i in
+// column order, a quad's rows as (r0 + r1) + (r2 + r3), the block's quads as
+// (w0 + w1) + (w2 + w3) -- the pairwise tree over the block's rows.
 __global__ __launch_bounds__(256) void stepwise_readout_kernel(ReadArgs a) {
     __shared__ double red[kQuadsPerBlock][64];
     const int s = *a.base + a.k;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = blockIdx.y * 64 + lane;
-    double acc = 0.0;
+    double rs[4] = {0.0, 0.0, 0.0, 0.0};
     if (s < a.steps) {
         const int m = blockIdx.x * kQuadsPerBlock + wave;
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * m + j;
             if (i >= a.n) break;
             const int ci = nearest_state(a.U[(size_t)i * a.Rp + r], a.q);
+            double acc = 0.0;
             for (int64_t e = a.row_ptr[i]; e < a.row_ptr[i + 1]; ++e) {
-                const int cj = nearest_state(a.U[(size_t)a.col[e] * a.Rp + r], a.q);
+                const int c = a.col[e];
+                if (c <= i) continue;
+                const int cj = nearest_state(a.U[(size_t)c * a.Rp + r], a.q);
                 const double w = (double)a.J[e];
                 acc += (a.q == 2) ? (ci == cj ? w : -w) : (ci == cj ? w : 0.0);
             }
+            rs[j] = acc;
         }
     }
-    red[wave][lane] = acc;
+    red[wave][lane] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
     __syncthreads();
-    if (wave == 0 && s < a.steps) {
-        double tot = 0.0;
-        for (int w = 0; w < kQuadsPerBlock; ++w) tot += red[w][lane];
-        a.part[(size_t)blockIdx.x * a.Rp + r] = tot;
-    }
+    if (wave == 0 && s < a.steps)
+        a.part[(size_t)blockIdx.x * a.Rp + r] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
 struct BestArgs {
@@ -215,17 +220,18 @@ struct BestArgs {
     int last;         // 1 when this node reads out after the last step (forced)
 };
 
-// One workgroup per replica: H = -1/2 sum of the partials (fixed order),
-// trace entry, best-so-far and the colours of a new best.
+// One workgroup per replica: H = -(the pairwise tree over the blocks'
+// partials), trace entry, best-so-far and the colours of a new best.
 __global__ __launch_bounds__(256) void stepwise_best_kernel(BestArgs a) {
     __shared__ int improved;
+    __shared__ double stack[TreeAcc::kLevels];
     const int s = a.last ? a.steps - 1 : *a.base + a.k;
     if (s >= a.steps) return;
     const int r = blockIdx.x;
     if (threadIdx.x == 0) {
-        double tot = 0.0;
-        for (int b = 0; b < a.nblocks; ++b) tot += a.part[(size_t)b * a.Rp + r];
-        const double H = -0.5 * tot;
+        TreeAcc tree(stack);
+        for (int b = 0; b < a.nblocks; ++b) tree.push(a.part[(size_t)b * a.Rp + r]);
+        const double H = -tree.finish();
         const int kread = (s + a.M) / a.M - 1;
         if (a.trace) a.trace[(size_t)kread * a.R + r] = H;
         improved = (kread == 0 || H < a.best[r]) ? 1 : 0;

@@ -253,3 +253,38 @@ def gershgorin(g: Graph) -> float:
     s = np.zeros(g.n)
     np.add.at(s, np.repeat(np.arange(g.n), np.diff(g.row_ptr)), np.abs(g.w))
     return float(s.max()) if g.n else 0.0
+
+
+# ------------------------------------------------ benchmark schedules ----
+# The paper prints no K, Ks or noise values.  The benchmark workloads use
+# linear K ramps from 0 to k_mul * 0.5 / (dt * max_i sum_j |J_ij|), Ks either
+# a linear ramp to ks_mul * 0.5 / (dt * q) or the triangular annealing
+# waveform with that amplitude, and a constant noise amplitude; the
+# multipliers were frozen from sweeps on each workload before any timing.
+WORKLOAD_SCHEDULES = {
+    # plain Ising max-cut, G(800, 0.06) unit weights, 1000 steps
+    "gnp800": dict(q=2, k_mul=8.0, ks_mul=0.25, ks_shape="ramp", periods=0, sigma=0.1),
+    # sparse max-cut at scale, 100 x 100 +-1 torus, 10000 steps
+    "torus": dict(q=2, k_mul=2.0, ks_mul=1.0, ks_shape="triangle", periods=5, sigma=0.1),
+    # batched Potts 3-colouring, 1024 planted graphs, 5000 steps
+    "colouring": dict(q=3, k_mul=4.0, ks_mul=0.5, ks_shape="triangle", periods=10, sigma=0.2),
+    # dense SK, n = 4096 (the Gershgorin bound is loose for all-to-all
+    # couplings, hence the large K multiplier), 1000 steps
+    "sk": dict(q=2, k_mul=32.0, ks_mul=0.03, ks_shape="ramp", periods=0, sigma=0.1),
+    # adjoint schedule tuning, 128 x G(2000, 10/1999) +-1, 2000 steps
+    "adjoint": dict(q=2, k_mul=2.0, ks_mul=1.0, ks_shape="triangle", periods=5, sigma=0.1),
+}
+
+
+def workload_schedule(name: str, max_row_sum: float, steps: int, dt: float):
+    """(K, Ks, sigma, K_max, Ks_max) of a benchmark workload's frozen recipe."""
+    wl = WORKLOAD_SCHEDULES[name]
+    q = wl["q"]
+    kmax = wl["k_mul"] * 0.5 / (dt * max_row_sum)
+    ksmax = wl["ks_mul"] * 0.5 / (dt * q)
+    K = ramp(0.0, kmax, steps)
+    if wl["ks_shape"] == "triangle":
+        Ks = triangle(ksmax, wl["periods"], steps)
+    else:
+        Ks = ramp(0.0, ksmax, steps)
+    return K, Ks, const(wl["sigma"], steps), kmax, ksmax

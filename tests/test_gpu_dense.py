@@ -96,8 +96,8 @@ def test_dense_in_run_readout(oim, orc, prec):
     assert tr.shape == (3, R)
     np.testing.assert_array_equal(ro["best_h"], tr.min(axis=0))
     for r in range(R):
-        h = orc.h_model(rp, cl, Jv, 2, ro["best_colour"][r])
-        assert abs(h - ro["best_h"][r]) < 1e-9 * max(1.0, np.abs(J).sum())
+        # Eq. 1 at the best colours, in the oracle's fixed FP64 order: equal
+        assert ro["best_h"][r] == orc.h_model_fixed(rp, cl, Jv, 2, ro["best_colour"][r])
 
 
 def test_dense_rejects_unknown_precision(oim):

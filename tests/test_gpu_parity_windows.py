@@ -1,0 +1,205 @@
+"""GPU <-> FP64 oracle parity where the solver actually runs: 100-step
+windows late in each benchmark workload's own schedule (strong coupling,
+SHIL near its peak), on the full launch configurations the benchmark times,
+with sampled replicas or graphs checked one by one against the oracle.
+
+Every window starts from the oracle's own state: the oracle integrates the
+sampled replicas (or graphs) from theta0 through the schedule up to the
+window, the result is rounded to FP32, and both sides integrate the window
+from those FP32 phases with the global step index of the window (noise
+counter).  The other replicas of the launch start from uniform phases; they
+are independent of the sampled ones.  Tolerance: 1e-5 rad for the FP32
+paths."""
+import numpy as np
+import pytest
+
+import synth
+from _util import DT, wrapdiff
+
+pytestmark = pytest.mark.gpu
+TOL_RAD = 1e-5
+
+
+@pytest.fixture(scope="module")
+def oim():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2505_22631_amd as m
+    m.lib()
+    return m
+
+
+def _t(x):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def _gpu(oim, prob, th, K, Ks, sg, sd, q, step0, flags=0):
+    import torch
+    d = _t(th)
+    oim.run(prob, d, _t(K), _t(Ks), _t(sg), _t(sd), q=q, dt=DT, step0=step0, flags=flags)
+    torch.cuda.synchronize()
+    return d.cpu().numpy()
+
+
+def _window_start(orc, g, J, th0_rows, K, Ks, sg, sd, q, T0, instance=0):
+    """Oracle state at step T0 of the schedule, as FP32."""
+    out = orc.run_csr(g.row_ptr, g.col, J, th0_rows, q=q, dt=DT, K=K[:T0], Ks=Ks[:T0],
+                      sigma=sg[:T0], seeds=sd, instance=instance)
+    return out.astype(np.float32)
+
+
+def _sparse_window(oim, orc, g, name, R, steps, T0, sample, flags=0, check_loops=(0,)):
+    J = (-g.w).astype(np.float32)
+    with oim.Problem.from_csr(g.n, g.row_ptr, g.col, J) as prob:
+        K, Ks, sg, _, _ = synth.workload_schedule(name, prob.info["max_abs_row_sum"], steps, DT)
+        q = synth.WORKLOAD_SCHEDULES[name]["q"]
+        th = synth.theta0(R, g.n, seed=100)
+        sd = synth.seeds(R, 0)
+        start = _window_start(orc, g, J, th[sample], K, Ks, sg, sd[sample], q, T0)
+        th[sample] = start
+        W = slice(T0, T0 + 100)
+        want = orc.run_csr(g.row_ptr, g.col, J, start, q=q, dt=DT, K=K[W], Ks=Ks[W],
+                           sigma=sg[W], seeds=sd[sample], step0=T0)
+        for fl in check_loops:
+            got = _gpu(oim, prob, th, K[W].copy(), Ks[W].copy(), sg[W].copy(), sd, q, T0,
+                       flags=fl)
+            err = wrapdiff(got[sample], want).max()
+            print(f"{name} R={R} window [{T0}, {T0 + 100}) K={K[T0]:.3g} Ks={Ks[T0]:.3g} "
+                  f"loop={fl}: max |dtheta| = {err:.3e} rad", flush=True)
+            assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+            assert err < TOL_RAD
+
+
+def test_gnp800_late_windows_full_launch(oim, orc):
+    # plain max-cut workload, 256 replicas (the batched launch), replicas 0,
+    # 131 and 255 checked, windows in the middle and at the end of the ramp
+    g = synth.erdos_renyi(800, 0.06, seed=0)
+    for T0 in (500, 900):
+        _sparse_window(oim, orc, g, "gnp800", 256, 1000, T0, [0, 131, 255])
+
+
+def test_gnp800_late_window_plain(oim, orc):
+    g = synth.erdos_renyi(800, 0.06, seed=0)
+    _sparse_window(oim, orc, g, "gnp800", 1, 1000, 900, [0])
+
+
+def test_torus_late_window_full_launch(oim, orc):
+    # the 100 x 100 torus with 256 replicas at the peak of the triangular
+    # SHIL (K at 90 % of its maximum); both loop forms
+    g = synth.torus(100, 100, seed=1, signed=True)
+    _sparse_window(oim, orc, g, "torus", 256, 10000, 9000, [0, 255],
+                   check_loops=(0, 2))  # OIM_LOOP_AUTO (LDS-resident), OIM_LOOP_STEPWISE
+
+
+def _colouring_batch():
+    graphs = [g for g, _ in synth.planted_batch(1024, 100, 600, 4.6, 3, seed=2)]
+    big, off = synth.block_diagonal(graphs)
+    return graphs, big, off
+
+
+@pytest.mark.parametrize("T0", [0, 4900])
+def test_colouring_full_batch_sampled_graphs(oim, orc, T0):
+    # the whole 1024-graph batch in one launch (the benchmark's launch shape,
+    # 512 threads x 1 slice per wave), 16 graphs checked one by one
+    graphs, big, off = _colouring_batch()
+    steps, q = 5000, 3
+    J = -np.ones(big.nnz, np.float32)
+    rng = np.random.default_rng(11)
+    pick = np.sort(rng.choice(1024, size=16, replace=False))
+    with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, J, off) as prob:
+        oim.oim_set_tuning(prob.handle, q, 512, 1)
+        K, Ks, sg, _, _ = synth.workload_schedule("colouring", prob.info["max_abs_row_sum"],
+                                                  steps, DT)
+        th = synth.theta0(1, big.n, seed=100)
+        sd = synth.seeds(1, 0)
+        starts = {}
+        for b in pick:
+            g = graphs[b]
+            Jb = -np.ones(g.nnz, np.float32)
+            sl = slice(off[b], off[b + 1])
+            if T0 > 0:
+                th[:, sl] = _window_start(orc, g, Jb, th[:, sl], K, Ks, sg, sd, q, T0, instance=b)
+            starts[b] = th[:, sl].copy()
+        W = slice(T0, T0 + 100)
+        got = _gpu(oim, prob, th, K[W].copy(), Ks[W].copy(), sg[W].copy(), sd, q, T0)
+    worst = 0.0
+    for b in pick:
+        g = graphs[b]
+        want = orc.run_csr(g.row_ptr, g.col, -np.ones(g.nnz), starts[b], q=q, dt=DT, K=K[W],
+                           Ks=Ks[W], sigma=sg[W], seeds=sd, step0=T0, instance=int(b))
+        worst = max(worst, wrapdiff(got[:, off[b]:off[b + 1]], want).max())
+    print(f"colouring batch window [{T0}, {T0 + 100}), graphs {pick.tolist()}: "
+          f"max |dtheta| = {worst:.3e} rad", flush=True)
+    assert worst < TOL_RAD
+
+
+def test_noise_stream_over_1e7_counters(oim, orc):
+    # K = Ks = 0: every phase moves by its noise kicks alone.  The 1024-graph
+    # batch (instance numbers b up to 1023), two replicas whose keys use both
+    # key words, 128 steps crossing t = 2^31: 2.3e7 Philox counters.  A wrong
+    # word anywhere moves a phase by ~0.05 rad.
+    graphs, big, off = _colouring_batch()
+    steps, q, R = 128, 3, 2
+    step0 = 2**31 - 64
+    J = -np.ones(big.nnz, np.float32)
+    sd = np.array([(1 << 40) + 1, 7], np.uint64)
+    th = synth.theta0(R, big.n, seed=5)
+    z = np.zeros(steps, np.float32)
+    sg = synth.const(0.5, steps)
+    with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, J, off) as prob:
+        got = _gpu(oim, prob, th, z, z, sg, sd, q, step0)
+    want = orc.run_csr_blocks(big.row_ptr, big.col, J, off, th, q=q, dt=DT, K=z, Ks=z, sigma=sg,
+                              seeds=sd, step0=step0)
+    err = wrapdiff(got, want).max()
+    counters = R * sum((g.n + 3) // 4 for g in graphs) * steps
+    print(f"noise only: {counters:.3e} Philox counters, max |dtheta| = {err:.3e} rad", flush=True)
+    assert counters >= 10**7
+    assert err < TOL_RAD
+
+
+# ------------------------------------------------------------------ dense ----
+def _dense_case(oim, orc, T0, compress):
+    """Dense SK n = 4096 with 512 replicas (the benchmark's launch), window
+    [T0, T0 + 100) of its 1000-step schedule, replicas 0 and 511 checked.
+    With `compress`, the window's start state is the oracle's after a
+    100-step ramp of K from 0 to K[T0] (the full prefix costs ~10 minutes of
+    oracle time); T0 = 0 starts from uniform phases."""
+    n, R, steps, q = 4096, 512, 1000, 2
+    J = synth.sk_dense(n, seed=3)
+    Jd = J.astype(np.float64)
+    sample = [0, R - 1]
+    out = {}
+    with oim.Problem.from_dense(J) as prob:
+        K, Ks, sg, _, _ = synth.workload_schedule("sk", prob.info["max_abs_row_sum"], steps, DT)
+        th = synth.theta0(R, n, seed=100)
+        sd = synth.seeds(R, 0)
+        if compress:
+            pk = synth.ramp(0.0, float(K[T0]), 100)
+            pre = orc.run_dense(Jd, th[sample], q=q, dt=DT, K=pk, Ks=synth.const(Ks[T0], 100),
+                                sigma=synth.const(sg[T0], 100), seeds=sd[sample],
+                                step0=T0 - 100)
+            th[sample] = pre.astype(np.float32)
+        W = slice(T0, T0 + 100)
+        want = orc.run_dense(Jd, th[sample], q=q, dt=DT, K=K[W], Ks=Ks[W], sigma=sg[W],
+                             seeds=sd[sample], step0=T0)
+        for prec in (oim.OIM_PREC_FP32, oim.OIM_PREC_BF16X3):
+            got = _gpu(oim, prob, th, K[W].copy(), Ks[W].copy(), sg[W].copy(), sd, q, T0,
+                       flags=prec)
+            assert np.all(np.isfinite(got)) and got.min() >= 0 and got.max() < 2 * np.pi
+            out[prec] = wrapdiff(got[sample], want).max()
+            print(f"dense SK n={n} R={R} window [{T0}, {T0 + 100}) K={K[T0]:.3g} "
+                  f"prec={'fp32' if prec == 0 else 'bf16x3'}: max |dtheta| = {out[prec]:.3e} rad",
+                  flush=True)
+    return out
+
+
+def test_dense_full_size_100_steps(oim, orc):
+    errs = _dense_case(oim, orc, 0, False)
+    assert errs[0] < TOL_RAD
+
+
+def test_dense_full_size_late_window(oim, orc):
+    errs = _dense_case(oim, orc, 900, True)
+    assert errs[0] < TOL_RAD
