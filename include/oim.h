@@ -39,6 +39,8 @@
  *     device memory untouched.  oim_last_error() holds a per-thread detail
  *     string for the last failure.
  *   - A problem may be used by one stream at a time.
+ *   - A handle is a number that is never reused: using it after
+ *     oim_problem_destroy returns OIM_E_STATE.
  */
 #ifndef OIM_H
 #define OIM_H
@@ -174,12 +176,16 @@ typedef struct {
  * batched sweep of annealing schedules, as in Sec. III-D / Fig. 3b).
  * seeds: device uint64 [R].  step0: global index of the first step (noise
  * counter).  theta: device FP32 [R][n], overwritten with the final phases in
- * [0, 2pi).  phase: NULL, or device uint32 [R][n] phase words; when given,
+ * [0, 2pi); an input phase that is NaN or infinite is taken as 0.  phase: NULL, or device uint32 [R][n] phase words; when given,
  * the initial state is read from phase (theta's input is ignored) and the
  * final state is written to both.  Resuming with the phase words of a
  * previous call, step0 = its end and the schedule suffix reproduces an
  * uninterrupted run bit for bit.  steps = 0 does no device work.
- * readout may be NULL.  Errors: OIM_E_ARG, OIM_E_UNSUPPORTED (e.g. BF16X3 on
+ * readout may be NULL.  The call only enqueues work on `stream` (every loop
+ * form); the stepwise form captures its step loop into a hipGraph on the
+ * first call for a launch shape (q, R, readout period) and replays the cached
+ * graph on later calls, and its workspace is cached in p (both freed by
+ * oim_problem_destroy).  Errors: OIM_E_ARG, OIM_E_UNSUPPORTED (e.g. BF16X3 on
  * a sparse problem, PERSISTENT when a replica does not fit in LDS),
  * OIM_E_NOMEM, OIM_E_HIP. */
 int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
@@ -206,7 +212,9 @@ typedef struct {
 /* Times every launch variant that covers the problem's largest instance on
  * the first trial_steps steps of the given schedules (device arrays of at
  * least cfg->steps entries; seeds [R]; theta [R][n] device, read only: the
- * trials run on a scratch copy, without readout), then the four fastest again
+ * trials run on a scratch copy, without readout; with OIM_SCHED_PER_REPLICA
+ * the schedules are [R][cfg->steps] and each replica runs the first steps of
+ * its own row), then the four fastest again
  * three times on min(cfg->steps, 2 trial_steps) steps, and keeps the one with
  * the smallest median for later oim_run calls on p with the same SHIL order
  * class (q = 2, q = 3, other).  cfg gives q, R, dt; its steps must be
@@ -235,6 +243,14 @@ int oim_theta_from_phase(int64_t count, const uint32_t* phase, float* theta, hip
 
 /* ------------------------------------------------------------------------
  * Readout (Sec. III-B phase threshold kernel; Eq. 1, 2, 6).
+ *
+ * Every FP64 sum of these readouts, and of the in-run readouts of oim_run,
+ * follows one fixed order: each row i sums its terms over the upper triangle
+ * j > i in ascending column order, starting from +0; the row sums are
+ * combined by the pairwise tree over rows (zero-padded to a power of two,
+ * adjacent pairs first, lower rows on the left).  The values are therefore
+ * reproducible bit for bit from identical colours, on any loop form, and for
+ * integer weights (exact in any order) they equal the exact sums.
  * ---------------------------------------------------------------------- */
 
 /* colour[k] = floor(fmaf(theta[k], (float)(q / 2pi), 0.5f)) mod q for

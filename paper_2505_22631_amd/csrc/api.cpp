@@ -43,10 +43,11 @@ void release(Problem* p) {
     hipFree(p->d_sell);
     hipFree(p->d_inst);
     hipFree(p->d_order);
+    stepwise_release(p);
     hipFree(p->d_work);
     hipFree(p->d_adj);
     dense_release(p);
-    p->magic = kDeadMagic;
+    unregister_problem(p);
     delete p;
 }
 
@@ -165,7 +166,7 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
         release(p);
         return st;
     }
-    *out = reinterpret_cast<oim_problem>(p);
+    *out = register_problem(p);
     return OIM_OK;
 }
 
@@ -212,7 +213,7 @@ __attribute__((visibility("default"))) int oim_problem_from_dense(int32_t n, con
         release(p);
         return st;
     }
-    *out = reinterpret_cast<oim_problem>(p);
+    *out = register_problem(p);
     return OIM_OK;
 }
 

@@ -11,8 +11,6 @@
 
 namespace oim {
 
-constexpr uint32_t kProblemMagic = 0x4f494d50u;  // "OIMP"
-constexpr uint32_t kDeadMagic = 0xdeadbeefu;
 constexpr int kMaxQ = 16;
 constexpr int kSliceQuads = 64;  // quads (4 oscillators) per slice = one wave's lanes
 constexpr int kAdjMaxN = 4096;   // largest instance the adjoint kernels hold in LDS
@@ -39,7 +37,7 @@ struct SellImage {
 };
 
 struct Problem {
-    uint32_t magic = kProblemMagic;
+    uint64_t handle = 0;  // registry key, the value callers hold as oim_problem
     int device = 0;
     int32_t n = 0;
     int64_t nnz = 0;
@@ -78,6 +76,8 @@ struct Problem {
     // cached workspace for the stepwise / dense loops
     void* d_work = nullptr;
     size_t work_bytes = 0;
+    // captured step loops of the stepwise form (stepwise.hip), by launch shape
+    void* step_plans = nullptr;
 
     // launch variant of the LDS-resident kernel chosen by the autotuner, per
     // SHIL order class (generic, q = 2, q = 3); 0 = not tuned
@@ -99,7 +99,13 @@ int validate_csr(int32_t n, int64_t nnz, const int64_t* row_ptr, const int32_t* 
                  const float* J);
 int validate_dense(int32_t n, const float* J);
 int validate_cfg(const Problem* p, const oim_run_cfg* cfg);
-Problem* checked(oim_problem p);
+// Handle registry: a problem is known by a number that is never reused, so a
+// handle used after oim_problem_destroy is detected without touching freed
+// memory.  register_problem fills p->handle; checked() returns the live
+// problem of a handle or null; unregister_problem forgets it.
+oim_problem register_problem(Problem* p);
+Problem* checked(oim_problem h);
+void unregister_problem(Problem* p);
 int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t n_inst,
                     const int32_t* inst_off);
 void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
@@ -114,6 +120,7 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
                            const float* sigma, const uint64_t* seeds, int64_t step0,
                            float* theta, uint32_t* phase, const oim_readout* ro,
                            hipStream_t stream);
+void stepwise_release(Problem* p);
 int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                  const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
                  uint32_t* phase, const oim_readout* ro, hipStream_t stream);

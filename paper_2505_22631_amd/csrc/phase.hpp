@@ -2,8 +2,8 @@
 //
 // A phase is held as a 32-bit fixed-point fraction of a turn,
 // u = theta / 2pi * 2^32 (mod 2^32), like the phase accumulator of a
-// numerically controlled oscillator.  The wrap of Algorithm 1 ("keep phases in
-// [0,1)") is then exact integer overflow, and the state resolution is
+// numerically controlled oscillator.  The wrap of Algorithm 1 (the phase
+// normalised to one turn) is then exact integer overflow, and the state resolution is
 // 2^-32 turn (1.5e-9 rad) instead of FP32's 4.8e-7 rad near 2pi, so rounding
 // of the state no longer accumulates over the steps.  All dynamics arithmetic
 // stays FP32: increments are computed in FP32 in units of 2^-32 turn and
@@ -31,8 +31,10 @@ __device__ __forceinline__ uint32_t advance(uint32_t u, float du) {
     return u + (uint32_t)(int32_t)__builtin_rintf(du);
 }
 
-// Radians (any finite value) -> phase word, FP64 conversion.
+// Radians -> phase word, FP64 conversion; a non-finite phase (NaN, +-Inf)
+// is taken as 0.
 __device__ __forceinline__ uint32_t phase_from_theta(float th) {
+    if (!__builtin_isfinite(th)) return 0u;
     const double x = (double)th / kTwoPiD;
     const double f = x - __builtin_floor(x);                      // [0, 1]
     const double w = __builtin_rint(f * 4294967296.0);             // [0, 2^32]

@@ -69,7 +69,7 @@ __global__ __launch_bounds__(256) void phase_convert_kernel(int64_t count, const
          k += (int64_t)gridDim.x * blockDim.x) {
         if (theta_in) {
             const float th = theta_in[k];
-            phase_out[k] = __builtin_isfinite(th) ? phase_from_theta(th) : 0u;
+            phase_out[k] = phase_from_theta(th);
         } else {
             theta_out[k] = theta_from_phase(phase_in[k]);
         }

@@ -476,10 +476,12 @@ bool persistent_sparse_fits(const Problem* p) {
 }
 
 namespace {
+// sched_stride: the row length of per-replica schedules ([R][sched_stride]),
+// or 0 for one schedule shared by every replica.
 int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                    const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
                    uint32_t* phase, const oim_readout* ro, hipStream_t stream,
-                   const Variant* forced) {
+                   const Variant* forced, int32_t sched_stride) {
     const int S = p->max_slices;
     const Variant* v = forced ? forced : run_variant(p, cfg->q);
     if (!v || !persistent_sparse_fits(p))
@@ -509,7 +511,7 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
     a.best_step = ro ? ro->best_step : nullptr;
     a.best_colour = ro ? ro->best_colour : nullptr;
     a.R = cfg->R;
-    a.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
+    a.sched_stride = sched_stride;
     const int qi = cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0;
     KernelFn fn = v->fn[qi];
     const size_t lds = lds_bytes(plane, v->tb);
@@ -529,7 +531,8 @@ int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const flo
                              const float* Ks, const float* sigma, const uint64_t* seeds,
                              int64_t step0, float* theta, uint32_t* phase,
                              const oim_readout* ro, hipStream_t stream) {
-    return launch_variant(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, nullptr);
+    return launch_variant(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, nullptr,
+                          (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0);
 }
 
 // Autotuner: every variant whose waves cover the largest instance runs the
@@ -557,6 +560,9 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
         st = hip_error(e, "autotune events");
     oim_run_cfg c = *cfg;
     c.readout_every = 0;
+    // per-replica schedules keep the caller's row length while the trials
+    // run a prefix of each row
+    const int32_t stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
     // times one variant `reps` times on `steps` steps of the schedule
     auto time_variant = [&](const Variant& v, int steps, int reps, float* out) {
         c.steps = steps;
@@ -566,7 +572,8 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
                 st = hip_error(e, "autotune copy");
                 break;
             }
-            st = launch_variant(p, &c, K, Ks, sigma, seeds, 0, scratch, nullptr, nullptr, stream, &v);
+            st = launch_variant(p, &c, K, Ks, sigma, seeds, 0, scratch, nullptr, nullptr, stream, &v,
+                                stride);
             if (st) break;
             float ms = 0.f;
             if ((e = hipEventRecord(e1, stream)) != hipSuccess ||

@@ -10,16 +10,22 @@
 // gather is one coalesced 512-byte load.  Lane r draws the quad's four
 // normals with one Philox call keyed by replica r's seed.
 //
-// The step loop is captured once into a hipGraph of `chunk` step kernels
-// plus a node that advances a device-resident step base; the executable
-// graph is replayed ceil(steps / chunk) times (step kernels past the last
-// step return at once).  In-run readouts are graph nodes too (chunk is a
-// multiple of the readout period), with the final partial readout launched
-// after the replays.
+// The step loop is a hipGraph of `chunk` step kernels plus a node that
+// advances a device-resident step base; the executable graph is replayed
+// ceil(steps / chunk) times (step kernels past the last step return at
+// once).  In-run readouts are graph nodes too (chunk is a multiple of the
+// readout period), with the final partial readout launched after the
+// replays.  Everything a call changes (schedule, seed and readout pointers,
+// first step, step count) lives in a small device block that the captured
+// kernels read, written by a one-thread kernel at the start of each call, so
+// a graph is captured once per problem and launch shape (q, R, readout
+// period, chunk) and kept in the problem's plan cache; a call enqueues work
+// and returns without waiting for it.
 #include <float.h>
 
 #include <algorithm>
 #include <cmath>
+#include <new>
 
 #include "internal.hpp"
 #include "noise.hpp"
@@ -32,6 +38,21 @@ namespace {
 
 constexpr int kQuadsPerBlock = 4;  // one per wave, 256 threads
 
+// Per-call arguments, in device memory (see the header comment).
+struct CallArgs {
+    const float* K;
+    const float* Ks;
+    const float* sigma;
+    const uint64_t* seeds;
+    double* trace;        // [ceil(steps/M)][R] or null
+    int8_t* best_colour;  // [R][n] or null
+    int64_t step0;        // global index of local step 0
+    int32_t steps;
+    int32_t sched_stride; // 0: one schedule for all replicas; steps: [R][steps]
+    float dt;
+    int32_t base;         // local index of node 0 of the current chunk
+};
+
 struct StepArgs {
     const int64_t* row_ptr;
     const int32_t* col;
@@ -39,34 +60,29 @@ struct StepArgs {
     uint32_t* U;          // [np][Rp]
     const float2* tin;    // [np][Rp]
     float2* tout;
-    const float* K;
-    const float* Ks;
-    const float* sigma;
-    const uint64_t* seeds;
-    const int* base;      // device step base (local index of node 0 of the chunk)
+    const CallArgs* call;
     int k;                // position of this node in the chunk
-    int steps, n, R, Rp, q;
-    int64_t step0;
-    float dt;
-    int sched_stride;     // 0: one schedule for all replicas; steps: [R][steps]
+    int n, R, Rp, q;
 };
 
 template <int QM>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
-    const int s = *a.base + a.k;
-    if (s >= a.steps) return;
+    const CallArgs& c = *a.call;
+    const int s = c.base + a.k;
+    if (s >= c.steps) return;
     const int lane = threadIdx.x & 63;
     const int m = blockIdx.x * kQuadsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (4 * m >= a.n) return;
     const int r = blockIdx.y * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
-    const uint32_t t = (uint32_t)(a.step0 + s);
-    const float sqrt_dt = __builtin_sqrtf(a.dt);
-    const int64_t so = (int64_t)(r < a.R ? r : 0) * a.sched_stride + s;
-    const float kc = -a.dt * a.K[so] * kTurnScale;
-    const float ks = -a.dt * a.Ks[so] * kTurnScale;
-    const float ns = a.sigma[so] * sqrt_dt * kTurnScale;
-    const uint64_t seed = r < a.R ? a.seeds[r] : 0ull;
+    const uint32_t t = (uint32_t)(c.step0 + s);
+    const float dt = c.dt;
+    const float sqrt_dt = __builtin_sqrtf(dt);
+    const int64_t so = (int64_t)(r < a.R ? r : 0) * c.sched_stride + s;
+    const float kc = -dt * c.K[so] * kTurnScale;
+    const float ks = -dt * c.Ks[so] * kTurnScale;
+    const float ns = c.sigma[so] * sqrt_dt * kTurnScale;
+    const uint64_t seed = r < a.R ? c.seeds[r] : 0ull;
     float z[4];
     normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
     // The quad's four rows are walked in lock-step, two edges of each per
@@ -127,7 +143,9 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     }
 }
 
-__global__ void advance_base_kernel(int* base, int chunk) { *base += chunk; }
+__global__ void advance_base_kernel(CallArgs* call, int chunk) { call->base += chunk; }
+
+__global__ void set_call_kernel(CallArgs* call, CallArgs v) { *call = v; }
 
 // [R][n] theta or phase words -> [np][Rp] phase words and table (both
 // tables get the initial values so padding is finite everywhere).
@@ -168,8 +186,9 @@ struct ReadArgs {
     const float* J;
     const uint32_t* U;
     double* part;  // [gridDim.x][Rp]
-    const int* base;
-    int k, steps, n, Rp, q;
+    const CallArgs* call;
+    int k;         // node position in the chunk, or -1: after the last step
+    int n, Rp, q;
 };
 
 // Partial sums of sum_{i<j} J_ij term(k_i, k_j) per block of 16 rows (four
@@ -179,11 +198,12 @@ struct ReadArgs {
 // (w0 + w1) + (w2 + w3) -- the pairwise tree over the block's rows.
 __global__ __launch_bounds__(256) void stepwise_readout_kernel(ReadArgs a) {
     __shared__ double red[kQuadsPerBlock][64];
-    const int s = *a.base + a.k;
+    const int steps = a.call->steps;
+    const int s = a.k < 0 ? steps - 1 : a.call->base + a.k;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int r = blockIdx.y * 64 + lane;
     double rs[4] = {0.0, 0.0, 0.0, 0.0};
-    if (s < a.steps) {
+    if (s < steps) {
         const int m = blockIdx.x * kQuadsPerBlock + wave;
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * m + j;
@@ -202,7 +222,7 @@ __global__ __launch_bounds__(256) void stepwise_readout_kernel(ReadArgs a) {
     }
     red[wave][lane] = (rs[0] + rs[1]) + (rs[2] + rs[3]);
     __syncthreads();
-    if (wave == 0 && s < a.steps)
+    if (wave == 0 && s < steps)
         a.part[(size_t)blockIdx.x * a.Rp + r] = (red[0][lane] + red[1][lane]) + (red[2][lane] + red[3][lane]);
 }
 
@@ -210,14 +230,11 @@ struct BestArgs {
     const double* part;
     int nblocks;
     const uint32_t* U;
-    double* trace;
     double* best;     // running best (workspace)
     int32_t* best_at; // running best step (workspace)
-    int8_t* best_colour;
-    const int* base;
-    int k, steps, M, n, R, Rp, q;
-    int64_t step0;
-    int last;         // 1 when this node reads out after the last step (forced)
+    const CallArgs* call;
+    int k;            // node position in the chunk, or -1: after the last step
+    int M, n, R, Rp, q;
 };
 
 // One workgroup per replica: H = -(the pairwise tree over the blocks'
@@ -225,25 +242,26 @@ struct BestArgs {
 __global__ __launch_bounds__(256) void stepwise_best_kernel(BestArgs a) {
     __shared__ int improved;
     __shared__ double stack[TreeAcc::kLevels];
-    const int s = a.last ? a.steps - 1 : *a.base + a.k;
-    if (s >= a.steps) return;
+    const CallArgs& c = *a.call;
+    const int s = a.k < 0 ? c.steps - 1 : c.base + a.k;
+    if (s >= c.steps) return;
     const int r = blockIdx.x;
     if (threadIdx.x == 0) {
         TreeAcc tree(stack);
         for (int b = 0; b < a.nblocks; ++b) tree.push(a.part[(size_t)b * a.Rp + r]);
         const double H = -tree.finish();
         const int kread = (s + a.M) / a.M - 1;
-        if (a.trace) a.trace[(size_t)kread * a.R + r] = H;
+        if (c.trace) c.trace[(size_t)kread * a.R + r] = H;
         improved = (kread == 0 || H < a.best[r]) ? 1 : 0;
         if (improved) {
             a.best[r] = H;
-            a.best_at[r] = (int32_t)(a.step0 + s + 1);
+            a.best_at[r] = (int32_t)(c.step0 + s + 1);
         }
     }
     __syncthreads();
-    if (improved && a.best_colour)
+    if (improved && c.best_colour)
         for (int i = threadIdx.x; i < a.n; i += blockDim.x)
-            a.best_colour[(size_t)r * a.n + i] = (int8_t)nearest_state(a.U[(size_t)i * a.Rp + r], a.q);
+            c.best_colour[(size_t)r * a.n + i] = (int8_t)nearest_state(a.U[(size_t)i * a.Rp + r], a.q);
 }
 
 int check_launch(const char* what) {
@@ -251,17 +269,52 @@ int check_launch(const char* what) {
     return e == hipSuccess ? OIM_OK : hip_error(e, what);
 }
 
-// releases what a failed capture left behind
-struct GraphGuard {
-    hipGraph_t g = nullptr;
-    hipGraphExec_t x = nullptr;
-    ~GraphGuard() {
-        if (x) hipGraphExecDestroy(x);
-        if (g) hipGraphDestroy(g);
-    }
+// One captured step loop: the executable graphs of a chunk (two when the
+// chunk is odd: the table parity then flips from replay to replay), the
+// workspace they were captured on, and an event recorded after their last
+// use so they can be destroyed safely.
+struct Plan {
+    int q = 0, R = 0, M = 0, chunk = 0;
+    const void* work = nullptr;
+    hipGraph_t g[2] = {nullptr, nullptr};
+    hipGraphExec_t x[2] = {nullptr, nullptr};
+    hipEvent_t done = nullptr;
+    uint64_t last_use = 0;
 };
 
+struct PlanCache {
+    static constexpr int kMax = 4;
+    Plan plans[kMax];
+    int count = 0;
+    uint64_t clock = 0;
+};
+
+void destroy_plan(Plan& pl) {
+    if (pl.done) {
+        (void)hipEventSynchronize(pl.done);
+        (void)hipEventDestroy(pl.done);
+    }
+    for (int i = 0; i < 2; ++i) {
+        if (pl.x[i]) (void)hipGraphExecDestroy(pl.x[i]);
+        if (pl.g[i]) (void)hipGraphDestroy(pl.g[i]);
+    }
+    pl = Plan{};
+}
+
+void clear_plans(Problem* p) {
+    PlanCache* c = static_cast<PlanCache*>(p->step_plans);
+    if (!c) return;
+    for (int i = 0; i < c->count; ++i) destroy_plan(c->plans[i]);
+    c->count = 0;
+}
+
 }  // namespace
+
+void stepwise_release(Problem* p) {
+    clear_plans(p);
+    delete static_cast<PlanCache*>(p->step_plans);
+    p->step_plans = nullptr;
+}
 
 int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                            const float* sigma, const uint64_t* seeds, int64_t step0,
@@ -277,9 +330,11 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     int chunk = std::min(steps, 64);
     if (M > 0) chunk = std::max(1, (std::min(steps, std::max(64, M)) / M)) * M;
     chunk = std::max(1, std::min(chunk, steps));
-    const size_t need = cells * (4 + 8 + 8) + (size_t)gx * Rp * 8 + (size_t)R * 12 + 256;
+    const size_t args_off = (cells * (4 + 8 + 8) + (size_t)gx * Rp * 8 + (size_t)R * 12 + 255) & ~(size_t)255;
+    const size_t need = args_off + 256;
     if (p->work_bytes < need) {
-        hipFree(p->d_work);
+        clear_plans(p);  // they were captured on the old workspace
+        (void)hipFree(p->d_work);
         p->d_work = nullptr;
         p->work_bytes = 0;
         hipError_t e = hipMalloc(&p->d_work, need);
@@ -290,6 +345,11 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
         }
         p->work_bytes = need;
     }
+    if (!p->step_plans) {
+        p->step_plans = new (std::nothrow) PlanCache();
+        if (!p->step_plans) return set_error(OIM_E_NOMEM, "plan cache");
+    }
+    PlanCache& cache = *static_cast<PlanCache*>(p->step_plans);
     unsigned char* w = static_cast<unsigned char*>(p->d_work);
     uint32_t* U = reinterpret_cast<uint32_t*>(w);
     float2* T0 = reinterpret_cast<float2*>(w + cells * 4);
@@ -297,14 +357,27 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     double* part = reinterpret_cast<double*>(T1 + cells);
     double* best = part + (size_t)gx * Rp;
     int32_t* best_at = reinterpret_cast<int32_t*>(best + R);
-    int* base = reinterpret_cast<int*>(best_at + R + 16);
+    CallArgs* call = reinterpret_cast<CallArgs*>(w + args_off);
 
+    // this call's arguments, for every kernel below (stream order)
+    CallArgs ca{};
+    ca.K = K;
+    ca.Ks = Ks;
+    ca.sigma = sigma;
+    ca.seeds = seeds;
+    ca.trace = ro ? ro->trace : nullptr;
+    ca.best_colour = ro ? ro->best_colour : nullptr;
+    ca.step0 = step0;
+    ca.steps = steps;
+    ca.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
+    ca.dt = cfg->dt;
+    ca.base = 0;
+    hipLaunchKernelGGL(set_call_kernel, dim3(1), dim3(1), 0, stream, call, ca);
+    int st = check_launch("set_call_kernel");
+    if (st) return st;
     hipLaunchKernelGGL(stepwise_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U, T0,
                        T1, n, R, np, Rp);
-    int st = check_launch("stepwise_init_kernel");
-    if (st) return st;
-    hipError_t e = hipMemsetAsync(base, 0, sizeof(int), stream);
-    if (e != hipSuccess) return hip_error(e, "reset step base");
+    if ((st = check_launch("stepwise_init_kernel"))) return st;
 
     using StepFn = void (*)(StepArgs);
     StepFn fn = cfg->q == 2 ? stepwise_step_kernel<2>
@@ -314,40 +387,28 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     sa.col = p->d_col;
     sa.J = p->d_J;
     sa.U = U;
-    sa.K = K;
-    sa.Ks = Ks;
-    sa.sigma = sigma;
-    sa.seeds = seeds;
-    sa.base = base;
-    sa.steps = steps;
+    sa.call = call;
     sa.n = n;
     sa.R = R;
     sa.Rp = Rp;
     sa.q = cfg->q;
-    sa.step0 = step0;
-    sa.dt = cfg->dt;
-    sa.sched_stride = (cfg->flags & OIM_SCHED_PER_REPLICA) ? cfg->steps : 0;
-    ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, base, 0, steps, n, Rp, cfg->q};
+    ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, call, 0, n, Rp, cfg->q};
     BestArgs ba{};
     ba.part = part;
     ba.nblocks = gx;
     ba.U = U;
-    ba.trace = ro ? ro->trace : nullptr;
     ba.best = best;
     ba.best_at = best_at;
-    ba.best_colour = ro ? ro->best_colour : nullptr;
-    ba.base = base;
-    ba.steps = steps;
+    ba.call = call;
     ba.M = M;
     ba.n = n;
     ba.R = R;
     ba.Rp = Rp;
     ba.q = cfg->q;
-    ba.step0 = step0;
 
     // Record one chunk: step kernels (with readouts where due) and the base
-    // advance.  Table parity alternates per step; chunk is even or the parity
-    // is carried by swapping the tables between replays.
+    // advance.  Table parity alternates per step; an odd chunk flips it from
+    // one replay to the next, so it has a graph for each parity.
     auto record_chunk = [&](hipStream_t s, bool parity) -> int {
         for (int k = 0; k < chunk; ++k) {
             const bool odd = ((k & 1) != 0) != parity;
@@ -362,57 +423,87 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
                 hipLaunchKernelGGL(stepwise_readout_kernel, dim3(gx, Rp / 64), dim3(256), 0, s, ra);
                 if ((rc = check_launch("stepwise_readout_kernel"))) return rc;
                 ba.k = k;
-                ba.last = 0;
                 hipLaunchKernelGGL(stepwise_best_kernel, dim3(R), dim3(256), 0, s, ba);
                 if ((rc = check_launch("stepwise_best_kernel"))) return rc;
             }
         }
-        hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, s, base, chunk);
+        hipLaunchKernelGGL(advance_base_kernel, dim3(1), dim3(1), 0, s, call, chunk);
         return check_launch("advance_base_kernel");
     };
 
-    const int replays = (steps + chunk - 1) / chunk;
-    const bool flip = (chunk & 1) != 0;  // an odd chunk flips the table parity each replay
-    GraphGuard g[2];
-    hipStream_t cap = nullptr;
-    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-    if (e != hipSuccess) return hip_error(e, "capture stream");
-    for (int par = 0; par < (flip ? 2 : 1); ++par) {
-        e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-        if (e != hipSuccess) {
-            hipStreamDestroy(cap);
-            return hip_error(e, "hipStreamBeginCapture");
-        }
-        st = record_chunk(cap, par == 1);
-        e = hipStreamEndCapture(cap, &g[par].g);
-        if (st || e != hipSuccess) {
-            hipStreamDestroy(cap);
-            return st ? st : hip_error(e, "hipStreamEndCapture");
-        }
-        e = hipGraphInstantiate(&g[par].x, g[par].g, nullptr, nullptr, 0);
-        if (e != hipSuccess) {
-            hipStreamDestroy(cap);
-            return hip_error(e, "hipGraphInstantiate");
+    const bool flip = (chunk & 1) != 0;
+    Plan* plan = nullptr;
+    for (int i = 0; i < cache.count; ++i) {
+        Plan& c = cache.plans[i];
+        if (c.q == cfg->q && c.R == R && c.M == M && c.chunk == chunk && c.work == p->d_work) {
+            plan = &c;
+            break;
         }
     }
-    hipStreamDestroy(cap);
+    hipError_t e = hipSuccess;
+    if (!plan) {
+        // capture a new plan, evicting the least recently used one if full
+        int slot = cache.count;
+        if (cache.count == PlanCache::kMax) {
+            slot = 0;
+            for (int i = 1; i < cache.count; ++i)
+                if (cache.plans[i].last_use < cache.plans[slot].last_use) slot = i;
+            destroy_plan(cache.plans[slot]);
+        } else {
+            ++cache.count;
+        }
+        Plan& pl = cache.plans[slot];
+        pl = Plan{};
+        hipStream_t cap = nullptr;
+        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+        if (e != hipSuccess) st = hip_error(e, "capture stream");
+        for (int par = 0; par < (flip ? 2 : 1) && !st; ++par) {
+            e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                st = hip_error(e, "hipStreamBeginCapture");
+                break;
+            }
+            st = record_chunk(cap, par == 1);
+            e = hipStreamEndCapture(cap, &pl.g[par]);
+            if (!st && e != hipSuccess) st = hip_error(e, "hipStreamEndCapture");
+            if (!st && (e = hipGraphInstantiate(&pl.x[par], pl.g[par], nullptr, nullptr, 0)) != hipSuccess)
+                st = hip_error(e, "hipGraphInstantiate");
+        }
+        if (cap) (void)hipStreamDestroy(cap);
+        if (!st && (e = hipEventCreateWithFlags(&pl.done, hipEventDisableTiming)) != hipSuccess)
+            st = hip_error(e, "plan event");
+        if (st) {
+            destroy_plan(pl);
+            // keep the cache dense: move the last plan into the freed slot
+            if (slot != cache.count - 1) {
+                pl = cache.plans[cache.count - 1];
+                cache.plans[cache.count - 1] = Plan{};
+            }
+            --cache.count;
+            return st;
+        }
+        pl.q = cfg->q;
+        pl.R = R;
+        pl.M = M;
+        pl.chunk = chunk;
+        pl.work = p->d_work;
+        plan = &pl;
+    }
+    plan->last_use = ++cache.clock;
+
+    const int replays = (steps + chunk - 1) / chunk;
     for (int c = 0; c < replays; ++c) {
-        e = hipGraphLaunch(g[flip ? (c & 1) : 0].x, stream);
+        e = hipGraphLaunch(plan->x[flip ? (c & 1) : 0], stream);
         if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
     }
+    e = hipEventRecord(plan->done, stream);
+    if (e != hipSuccess) return hip_error(e, "plan event record");
     // readout after the last step when steps is not a multiple of M
     if (M > 0 && steps % M != 0) {
-        ra.k = 0;
-        // the base now points past the end; a node reading "last" ignores it
-        BestArgs bl = ba;
-        bl.last = 1;
         ReadArgs rl = ra;
-        rl.base = nullptr;
-        // readout kernel with an explicit step: reuse the base slot
-        e = hipMemsetAsync(base, 0, sizeof(int), stream);
-        if (e != hipSuccess) return hip_error(e, "reset step base");
-        rl.base = base;
-        rl.k = steps - 1;
+        rl.k = -1;
+        BestArgs bl = ba;
+        bl.k = -1;
         hipLaunchKernelGGL(stepwise_readout_kernel, dim3(gx, Rp / 64), dim3(256), 0, stream, rl);
         if ((st = check_launch("stepwise_readout_kernel"))) return st;
         hipLaunchKernelGGL(stepwise_best_kernel, dim3(R), dim3(256), 0, stream, bl);
@@ -429,12 +520,7 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
         }
     }
     hipLaunchKernelGGL(stepwise_final_kernel, dim3(2048), dim3(256), 0, stream, U, theta, phase, n, R, Rp);
-    st = check_launch("stepwise_final_kernel");
-    if (st) return st;
-    // the graphs are destroyed on return; wait until the replays are done
-    e = hipStreamSynchronize(stream);
-    if (e != hipSuccess) return hip_error(e, "stepwise sync");
-    return OIM_OK;
+    return check_launch("stepwise_final_kernel");
 }
 
 }  // namespace oim

@@ -5,7 +5,9 @@
 #include <climits>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <unordered_map>
 
 #include "internal.hpp"
 
@@ -92,10 +94,30 @@ int validate_dense(int32_t n, const float* J) {
     return OIM_OK;
 }
 
-Problem* checked(oim_problem p) {
-    Problem* pr = reinterpret_cast<Problem*>(p);
-    if (!pr || pr->magic != kProblemMagic) return nullptr;
-    return pr;
+namespace {
+std::mutex g_registry_mu;
+std::unordered_map<uint64_t, Problem*> g_registry;
+uint64_t g_next_handle = 1;
+}  // namespace
+
+oim_problem register_problem(Problem* p) {
+    std::lock_guard<std::mutex> lock(g_registry_mu);
+    p->handle = g_next_handle++;
+    g_registry.emplace(p->handle, p);
+    return reinterpret_cast<oim_problem>(static_cast<uintptr_t>(p->handle));
+}
+
+Problem* checked(oim_problem h) {
+    const uint64_t key = static_cast<uint64_t>(reinterpret_cast<uintptr_t>(h));
+    if (key == 0) return nullptr;
+    std::lock_guard<std::mutex> lock(g_registry_mu);
+    const auto it = g_registry.find(key);
+    return it == g_registry.end() ? nullptr : it->second;
+}
+
+void unregister_problem(Problem* p) {
+    std::lock_guard<std::mutex> lock(g_registry_mu);
+    g_registry.erase(p->handle);
 }
 
 int validate_cfg(const Problem* p, const oim_run_cfg* cfg) {
