@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define OIM_ABI_VERSION 1
+#define OIM_ABI_VERSION 2
 
 typedef enum {
     OIM_OK = 0,
@@ -195,17 +195,22 @@ int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* 
 /* ------------------------------------------------------------------------
  * Launch-shape autotuning of the LDS-resident loop (the per-thread batch of
  * oscillators of Sec. III-C, chosen by measurement).  A launch variant is a
- * workgroup size (64 ... 1024 threads) and a number of 64-quad slices per
- * wave; any variant gives bit-identical results, only the speed differs.
+ * workgroup size (64 ... 1024 threads), a number of 64-quad slices per wave
+ * group and a number of rows of each quad of 4 oscillators per lane: 4 (a
+ * lane owns whole quads) or 2 or 1 (the waves of a group split each quad's
+ * rows, which keeps every wave busy on instances of few slices with long
+ * rows).  Any variant gives bit-identical results, only the speed differs.
  * ---------------------------------------------------------------------- */
-#define OIM_TUNE_MAX 48
+#define OIM_TUNE_MAX 64
 typedef struct {
     int32_t n_tried;                          /* variants timed (<= OIM_TUNE_MAX listed) */
     int32_t chosen_block;                     /* threads per workgroup of the winner */
     int32_t chosen_slices_per_wave;
+    int32_t chosen_rows_per_lane;
     float chosen_ms;                          /* its median time in the final pass */
     int32_t block[OIM_TUNE_MAX];              /* every variant tried, in order */
     int32_t slices_per_wave[OIM_TUNE_MAX];
+    int32_t rows_per_lane[OIM_TUNE_MAX];
     float ms[OIM_TUNE_MAX];                   /* best of two timings, milliseconds */
 } oim_tune_report;
 
@@ -214,11 +219,10 @@ typedef struct {
  * least cfg->steps entries; seeds [R]; theta [R][n] device, read only: the
  * trials run on a scratch copy, without readout; with OIM_SCHED_PER_REPLICA
  * the schedules are [R][cfg->steps] and each replica runs the first steps of
- * its own row), then the four fastest again
- * three times on min(cfg->steps, 2 trial_steps) steps, and keeps the one with
- * the smallest median for later oim_run calls on p with the same SHIL order
- * class (q = 2, q = 3, other).  cfg gives q, R, dt; its steps must be
- * >= trial_steps >= 1.
+ * its own row), then the four fastest again three times on
+ * min(cfg->steps, 2 trial_steps) steps, and keeps the one with the smallest
+ * median for later oim_run calls on p with the same SHIL order class (q = 2,
+ * q = 3, other).  cfg gives q, R, dt; its steps must be >= trial_steps >= 1.
  * report may be NULL.  Synchronous (waits for the trials on stream).
  * Allocates and frees a scratch copy of theta.  Errors: OIM_E_ARG,
  * OIM_E_UNSUPPORTED (dense problem, or a replica that does not fit the
@@ -230,9 +234,10 @@ int oim_autotune(oim_problem p, const oim_run_cfg* cfg, const float* K, const fl
 /* Sets the launch variant for SHIL order q's class directly (a choice cached
  * from an earlier oim_autotune on a problem of the same shape); block = 0
  * returns to the default choice.  Errors: OIM_E_ARG (q out of range, no
- * such variant, or one whose waves do not cover the largest instance),
- * OIM_E_UNSUPPORTED (dense problem). */
-int oim_set_tuning(oim_problem p, int32_t q, int32_t block, int32_t slices_per_wave);
+ * such variant, or one whose waves do not cover the largest instance or
+ * whose LDS does not fit), OIM_E_UNSUPPORTED (dense problem). */
+int oim_set_tuning(oim_problem p, int32_t q, int32_t block, int32_t slices_per_wave,
+                   int32_t rows_per_lane);
 
 /* Phase words <-> radians for count elements (device arrays):
  * phase = rint(frac(theta / 2pi) * 2^32) mod 2^32 (FP64), and

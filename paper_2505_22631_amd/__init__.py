@@ -172,12 +172,14 @@ def oim_autotune(h, n, theta, K, Ks, sigma, seeds, *, q, dt, trial_steps, stream
                              ctypes.byref(rep), _stream(stream)))
     k = rep.n_tried
     return {"block": rep.chosen_block, "slices_per_wave": rep.chosen_slices_per_wave,
-            "ms": rep.chosen_ms,
-            "tried": [(rep.block[i], rep.slices_per_wave[i], rep.ms[i]) for i in range(k)]}
+            "rows_per_lane": rep.chosen_rows_per_lane, "ms": rep.chosen_ms,
+            "tried": [(rep.block[i], rep.slices_per_wave[i], rep.rows_per_lane[i], rep.ms[i])
+                      for i in range(k)]}
 
 
-def oim_set_tuning(h, q, block, slices_per_wave) -> None:
-    check(lib().oim_set_tuning(h, int(q), int(block), int(slices_per_wave)))
+def oim_set_tuning(h, q, block, slices_per_wave, rows_per_lane=4) -> None:
+    check(lib().oim_set_tuning(h, int(q), int(block), int(slices_per_wave),
+                               int(rows_per_lane)))
 
 
 def _adj_cfg(q, R, steps, dt, checkpoint_every):

@@ -33,13 +33,14 @@ class AdjointCfg(ctypes.Structure):
                 ("checkpoint_every", _i32), ("flags", _u32)]
 
 
-OIM_TUNE_MAX = 48
+OIM_TUNE_MAX = 64
 
 
 class TuneReport(ctypes.Structure):
     _fields_ = [("n_tried", _i32), ("chosen_block", _i32), ("chosen_slices_per_wave", _i32),
-                ("chosen_ms", _f32), ("block", _i32 * OIM_TUNE_MAX),
-                ("slices_per_wave", _i32 * OIM_TUNE_MAX), ("ms", _f32 * OIM_TUNE_MAX)]
+                ("chosen_rows_per_lane", _i32), ("chosen_ms", _f32),
+                ("block", _i32 * OIM_TUNE_MAX), ("slices_per_wave", _i32 * OIM_TUNE_MAX),
+                ("rows_per_lane", _i32 * OIM_TUNE_MAX), ("ms", _f32 * OIM_TUNE_MAX)]
 
 
 class ProblemInfo(ctypes.Structure):
@@ -69,7 +70,7 @@ PROTOTYPES = {
     "oim_energy": (ctypes.c_int, [_P, _i32, _i32, _P, _P, _P, _P, _P]),
     "oim_autotune": (ctypes.c_int, [_P, ctypes.POINTER(RunCfg), _P, _P, _P, _P, _P, _i32,
                                     ctypes.POINTER(TuneReport), _P]),
-    "oim_set_tuning": (ctypes.c_int, [_P, _i32, _i32, _i32]),
+    "oim_set_tuning": (ctypes.c_int, [_P, _i32, _i32, _i32, _i32]),
     "oim_adjoint_checkpoint_words": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg),
                                                     ctypes.POINTER(_i64)]),
     "oim_adjoint_forward": (ctypes.c_int, [_P, ctypes.POINTER(AdjointCfg), _P, _P, _P, _P, _i64,

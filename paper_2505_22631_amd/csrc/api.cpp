@@ -297,7 +297,8 @@ __attribute__((visibility("default"))) int oim_autotune(oim_problem h, const oim
 }
 
 __attribute__((visibility("default"))) int oim_set_tuning(oim_problem h, int32_t q, int32_t block,
-                                                          int32_t slices_per_wave) {
+                                                          int32_t slices_per_wave,
+                                                          int32_t rows_per_lane) {
     clear_error();
     Problem* p = checked(h);
     if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
@@ -306,14 +307,17 @@ __attribute__((visibility("default"))) int oim_set_tuning(oim_problem h, int32_t
     const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
     if (block == 0) {
         p->tuned_tb[qc] = p->tuned_ms[qc] = 0;
+        p->tuned_rpl[qc] = 4;
         return OIM_OK;
     }
-    if (!persistent_variant_fits(p, block, slices_per_wave))
+    if (!persistent_variant_fits(p, block, slices_per_wave, rows_per_lane))
         return set_error(OIM_E_ARG, "no launch variant (" + std::to_string(block) + ", " +
-                                        std::to_string(slices_per_wave) +
+                                        std::to_string(slices_per_wave) + ", " +
+                                        std::to_string(rows_per_lane) +
                                         ") covering the largest instance");
     p->tuned_tb[qc] = (int16_t)block;
     p->tuned_ms[qc] = (int16_t)slices_per_wave;
+    p->tuned_rpl[qc] = (int16_t)rows_per_lane;
     return OIM_OK;
 }
 

@@ -83,6 +83,7 @@ struct Problem {
     // SHIL order class (generic, q = 2, q = 3); 0 = not tuned
     int16_t tuned_tb[3] = {0, 0, 0};
     int16_t tuned_ms[3] = {0, 0, 0};
+    int16_t tuned_rpl[3] = {4, 4, 4};
 
     // cached scratch of the adjoint backward pass
     void* d_adj = nullptr;
@@ -129,7 +130,7 @@ void dense_release(Problem* p);
 int launch_phase_convert(int64_t count, const float* theta_in, uint32_t* phase_out,
                          const uint32_t* phase_in, float* theta_out, hipStream_t s);
 bool persistent_sparse_fits(const Problem* p);
-bool persistent_variant_fits(const Problem* p, int tb, int ms);
+bool persistent_variant_fits(const Problem* p, int tb, int ms, int rpl);
 int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                     const float* sigma, const uint64_t* seeds, const float* theta,
                     int32_t trial_steps, oim_tune_report* rep, hipStream_t stream);

@@ -66,4 +66,13 @@ __device__ __forceinline__ void normals4(uint32_t m, uint32_t t, uint32_t b, uin
     box_muller(x.z, x.w, z[2], z[3]);
 }
 
+// The two normals of one word pair (pair 0: oscillators 4m, 4m+1; pair 1:
+// 4m+2, 4m+3) of the same Philox call, bit-identical to those normals4
+// returns for them.
+__device__ __forceinline__ void normals2(uint32_t m, uint32_t t, uint32_t b, uint32_t k0,
+                                         uint32_t k1, int pair, float z[2]) {
+    const u32x4 x = philox4x32_10(u32x4{m, t, b, 0u}, k0, k1);
+    box_muller(pair ? x.z : x.x, pair ? x.w : x.y, z[0], z[1]);
+}
+
 }  // namespace oim

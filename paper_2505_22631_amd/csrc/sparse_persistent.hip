@@ -89,7 +89,15 @@ __device__ __forceinline__ float2 sc_at(const unsigned char*, int byte_off) {
     return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
 }
 
-template <int TB, int MS, int QM>
+// Launch shape: TB threads (W = TB / 64 waves), MS slices per wave group,
+// RPL rows of every quad per lane.  RPL = 4: a lane owns whole quads (one
+// wave per slice).  RPL = 2 or 1 (rows split): G = 4 / RPL waves share a
+// slice, wave w owning rows g * RPL .. g * RPL + RPL - 1 of each quad of its
+// slices (g = w % G), so instances with few slices and long rows keep every
+// wave busy.  Every oscillator's arithmetic -- its row's multiply-adds in
+// entry order, its Philox normal, its update -- is the same in all shapes,
+// so they give identical results.
+template <int TB, int MS, int QM, int RPL>
 __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     // workgroup -> (instance, replica): all replicas of the largest instance first
@@ -98,15 +106,21 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     const int4 idesc = a.inst[inst_id];
     const int slice0 = idesc.x, S = idesc.y, off = idesc.z, n = idesc.w;
     const int plane = S * 64;
+    constexpr int W = TB / 64;
+    constexpr int G = 4 / RPL;     // waves per slice
+    constexpr int WS = W / G;      // wave groups (slices in flight)
+    constexpr int U = 8 / RPL;     // 16-byte entry loads per row per iteration
     float2* sc = reinterpret_cast<float2*>(smem);                   // [4 * plane]
     unsigned char* col8 = smem + (size_t)8 * 4 * plane;            // [4 * plane] (readout)
     double* red = reinterpret_cast<double*>(col8 + ((4 * plane + 15) & ~15));  // [W]
-    double* tstack = red + TB / 64;                                             // tree levels
+    double* tstack = red + W;                                                   // tree levels
     int* flag = reinterpret_cast<int*>(tstack + kSliceTreeLevels);
+    double* part = reinterpret_cast<double*>(flag + 4);             // [WS][G][64], RPL < 4
 
-    constexpr int W = TB / 64;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = wave % G, ws = wave / G;
+    const int j0 = g * RPL;        // first row of the quad this wave owns
     const int q = QM ? QM : a.q;
     const uint64_t seed = a.seeds[r];
     const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -117,24 +131,25 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         __builtin_amdgcn_make_buffer_rsrc((void*)a.sell, (short)0, (int)a.sell_bytes, 0x00020000);
     const int voff = lane * 16;
 
-    uint32_t ph[MS][4];
-    float drift[MS][4];
+    uint32_t ph[MS][RPL];
+    float drift[MS][RPL];
     int sbase[MS], sdeg[MS];
 
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
-        const int slice = wave + k * W;
+        const int slice = ws + k * WS;
         const int2 d = slice < S ? a.desc[slice0 + slice] : make_int2(0, 0);
         sbase[k] = __builtin_amdgcn_readfirstlane(d.x);
         sdeg[k] = __builtin_amdgcn_readfirstlane(d.y);
         const int m = slice * 64 + lane;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int jj = 0; jj < RPL; ++jj) {
+            const int j = j0 + jj;
             const int i = 4 * m + j;
             const bool valid = slice < S && i < n;
             const uint32_t u = valid ? (pw ? pw[i] : phase_from_theta(th[i])) : 0u;
-            ph[k][j] = u;
-            drift[k][j] = 0.0f;
+            ph[k][jj] = u;
+            drift[k][jj] = 0.0f;
             if (slice < S) sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
         }
     }
@@ -178,22 +193,26 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         // ---- phase A: noise, and coupling sums over the sliced-ELL rows ----
         // The first edge loads of a slice are issued, then its Philox noise
         // is computed while they are in flight (the noise depends only on
-        // the replica, the quad and the step); 4 edges of each of the slice's
-        // 4 rows per iteration: 8 16-byte buffer loads (scalar offsets, no
-        // per-lane address math), 16 LDS reads.  drift then holds the whole
-        // increment of the step, noise included.
+        // the replica, the quad and the step); per iteration 8 16-byte buffer
+        // loads (scalar offsets, no per-lane address math) over the lane's
+        // rows -- 4 edges of each of 4 rows, 8 of 2 or 16 of 1 -- and 16 LDS
+        // reads.  drift then holds the whole increment of the step, noise
+        // included.
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
-            if (wave + k * W < S) {
-                const int m = (wave + k * W) * 64 + lane;
+            if (ws + k * WS < S) {
+                const int m = (ws + k * WS) * 64 + lane;
                 const int D2 = sdeg[k] >> 1;
-                int4 v[4][2];
+                int4 v[RPL][U];
+                // loads past the row end (possible only when U > 2, since
+                // rows hold an even number of 16-byte pairs) are skipped
                 auto load_iter = [&](int e2) __attribute__((always_inline)) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int soff = (sbase[k] + j * D2 + e2) * 1024;
-                        v[j][0] = load_pair(rsrc, voff, soff);
-                        v[j][1] = load_pair(rsrc, voff + 1024, soff);
+                    for (int jj = 0; jj < RPL; ++jj) {
+                        const int soff = (sbase[k] + (j0 + jj) * D2 + e2) * 1024;
+#pragma unroll
+                        for (int h = 0; h < U; ++h)
+                            if (h < 2 || e2 + h < D2) v[jj][h] = load_pair(rsrc, voff + h * 1024, soff);
                     }
                 };
                 if (D2 > 0) load_iter(0);
@@ -206,47 +225,63 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 // the sums below are complete; the empty asm keeps their
                 // computation here, in the shadow of the loads, instead of
                 // letting it sink to its use after the sums
-                normals4(mm, t, (uint32_t)inst_id, kk0, kk1, drift[k]);
-                asm volatile("" : "+v"(drift[k][0]), "+v"(drift[k][1]), "+v"(drift[k][2]),
-                             "+v"(drift[k][3]));
-                float A[4] = {0.f, 0.f, 0.f, 0.f}, B[4] = {0.f, 0.f, 0.f, 0.f};
-                for (int e2 = 0; e2 < D2; e2 += 2) {
+                if constexpr (RPL == 4) {
+                    normals4(mm, t, (uint32_t)inst_id, kk0, kk1, drift[k]);
+                    asm volatile("" : "+v"(drift[k][0]), "+v"(drift[k][1]), "+v"(drift[k][2]),
+                                 "+v"(drift[k][3]));
+                } else if constexpr (RPL == 2) {
+                    normals2(mm, t, (uint32_t)inst_id, kk0, kk1, g, drift[k]);
+                    asm volatile("" : "+v"(drift[k][0]), "+v"(drift[k][1]));
+                } else {
+                    float z2[2];
+                    normals2(mm, t, (uint32_t)inst_id, kk0, kk1, g >> 1, z2);
+                    drift[k][0] = (g & 1) ? z2[1] : z2[0];
+                    asm volatile("" : "+v"(drift[k][0]));
+                }
+                float A[RPL], B[RPL];
+#pragma unroll
+                for (int jj = 0; jj < RPL; ++jj) A[jj] = B[jj] = 0.f;
+                for (int e2 = 0; e2 < D2; e2 += U) {
                     if (e2 > 0) load_iter(e2);
-                    // all 16 neighbour reads of the iteration are in flight
+                    // all neighbour reads of the iteration are in flight
                     // before the first multiply-add consumes one
-                    float2 p[2][4][2];
+                    float2 p[U][RPL][2];
 #pragma unroll
-                    for (int h = 0; h < 2; ++h)
+                    for (int h = 0; h < U; ++h)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            p[h][j][0] = sc_at(smem, v[j][h].x);
-                            p[h][j][1] = sc_at(smem, v[j][h].z);
+                        for (int jj = 0; jj < RPL; ++jj) {
+                            if (h < 2 || e2 + h < D2) {
+                                p[h][jj][0] = sc_at(smem, v[jj][h].x);
+                                p[h][jj][1] = sc_at(smem, v[jj][h].z);
+                            }
                         }
 #pragma unroll
-                    for (int h = 0; h < 2; ++h) {
+                    for (int h = 0; h < U; ++h) {
+                        if (h < 2 || e2 + h < D2) {
 #pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p[h][j][0].y, A[j]);
-                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].y), p[h][j][0].x, B[j]);
-                            A[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p[h][j][1].y, A[j]);
-                            B[j] = __builtin_fmaf(__int_as_float(v[j][h].w), p[h][j][1].x, B[j]);
+                            for (int jj = 0; jj < RPL; ++jj) {
+                                A[jj] = __builtin_fmaf(__int_as_float(v[jj][h].y), p[h][jj][0].y, A[jj]);
+                                B[jj] = __builtin_fmaf(__int_as_float(v[jj][h].y), p[h][jj][0].x, B[jj]);
+                                A[jj] = __builtin_fmaf(__int_as_float(v[jj][h].w), p[h][jj][1].y, A[jj]);
+                                B[jj] = __builtin_fmaf(__int_as_float(v[jj][h].w), p[h][jj][1].x, B[jj]);
+                            }
                         }
                     }
                 }
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float2 own = sc[j * plane + m];
-                    const float coup = __builtin_fmaf(own.x, A[j], -(own.y * B[j]));
+                for (int jj = 0; jj < RPL; ++jj) {
+                    const float2 own = sc[(j0 + jj) * plane + m];
+                    const float coup = __builtin_fmaf(own.x, A[jj], -(own.y * B[jj]));
                     // sin(3 theta) = s (3 - 4 s^2) with its multiply-add fused
                     const float sq = QM == 3 ? own.x * __builtin_fmaf(-4.0f * own.x, own.x, 3.0f)
-                                             : sin_q<QM>(own.x, own.y, ph[k][j], q);
+                                             : sin_q<QM>(own.x, own.y, ph[k][jj], q);
                     // the deterministic part of the increment; which of its two
                     // products is fused keeps the rounding this kernel has
                     // always had (the SHIL term for q = 2, the coupling term
                     // otherwise), so results are unchanged bit for bit
                     const float det = QM == 2 ? __builtin_fmaf(ks, sq, kc * coup)
                                               : __builtin_fmaf(kc, coup, ks * sq);
-                    drift[k][j] = __builtin_fmaf(ns, drift[k][j], det);
+                    drift[k][jj] = __builtin_fmaf(ns, drift[k][jj], det);
                 }
             }
         }
@@ -255,17 +290,17 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         // ---- phase B: Euler-Maruyama update, wrap, table refresh ----
 #pragma unroll
         for (int k = 0; k < MS; ++k) {
-            const int slice = wave + k * W;
+            const int slice = ws + k * WS;
             const int m = slice * 64 + lane;
             // Rows past n are padding: they are advanced and stored like the
             // others (their slots exist in every plane) but no edge reads them,
             // which keeps per-lane masks out of the loop.
             if (slice < S) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t u = advance(ph[k][j], drift[k][j]);
-                    ph[k][j] = u;
-                    sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
+                for (int jj = 0; jj < RPL; ++jj) {
+                    const uint32_t u = advance(ph[k][jj], drift[k][jj]);
+                    ph[k][jj] = u;
+                    sc[(j0 + jj) * plane + m] = make_float2(sin_turn(u), cos_turn(u));
                 }
             }
         }
@@ -275,57 +310,73 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         if (a.M > 0 && ((s + 1) % a.M == 0 || s + 1 == a.steps)) {
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
-                const int slice = wave + k * W;
+                const int slice = ws + k * WS;
                 const int m = slice * 64 + lane;
                 if (slice < S) {
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        col8[j * plane + m] = (unsigned char)nearest_state(ph[k][j], q);
+                    for (int jj = 0; jj < RPL; ++jj)
+                        col8[(j0 + jj) * plane + m] = (unsigned char)nearest_state(ph[k][jj], q);
                 }
             }
             __syncthreads();
             // Eq. 1 / Eq. 2 in the library's fixed FP64 order: each row sums
             // its terms over j > i in column order (the ELL row is the CSR row,
-            // its padding adds zeros); a lane folds its quad's rows as
-            // (r0 + r1) + (r2 + r3) and the lanes by the xor butterfly
-            // (partner distance 1, 2, ..., 32), which is the pairwise tree
-            // over the slice's 256 rows; thread 0 folds the slices, in order,
-            // into the tree over slices, one round of W slices at a time.
+            // its padding adds zeros); a quad's rows fold as (r0 + r1) +
+            // (r2 + r3) and the lanes by the xor butterfly (partner distance
+            // 1, 2, ..., 32), which is the pairwise tree over the slice's 256
+            // rows; thread 0 folds the slices, in order, into the tree over
+            // slices, one round of WS slices at a time.
             TreeAccN<kSliceTreeLevels> tree(tstack);
 #pragma unroll
             for (int k = 0; k < MS; ++k) {
-                if (k * W >= S) break;  // uniform over the workgroup
-                const int slice = wave + k * W;
+                if (k * WS >= S) break;  // uniform over the workgroup
+                const int slice = ws + k * WS;
+                double v = 0.0;
                 if (slice < S) {
                     const int m = slice * 64 + lane;
                     const int D2 = sdeg[k] >> 1;
-                    double rs[4];
+                    double rs[RPL];
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
+                    for (int jj = 0; jj < RPL; ++jj) {
+                        const int j = j0 + jj;
                         const int ci = col8[j * plane + m];
                         const int own = 4 * m + j;
                         double row = 0.0;
                         for (int e2 = 0; e2 < D2; ++e2) {
-                            const int4 v = load_pair(rsrc, voff, (sbase[k] + j * D2 + e2) * 1024);
-                            const int c0 = col8[v.x >> 3], c1 = col8[v.z >> 3];
-                            const float w0 = __int_as_float(v.y), w1 = __int_as_float(v.w);
+                            const int4 e = load_pair(rsrc, voff, (sbase[k] + j * D2 + e2) * 1024);
+                            const int c0 = col8[e.x >> 3], c1 = col8[e.z >> 3];
+                            const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.w);
                             // upper triangle only: the neighbour's index from its slot
-                            const bool up0 = slot_index(v.x >> 3, plane) > own;
-                            const bool up1 = slot_index(v.z >> 3, plane) > own;
+                            const bool up0 = slot_index(e.x >> 3, plane) > own;
+                            const bool up1 = slot_index(e.z >> 3, plane) > own;
                             const float t0 = (q == 2) ? (ci == c0 ? w0 : -w0) : (ci == c0 ? w0 : 0.f);
                             const float t1 = (q == 2) ? (ci == c1 ? w1 : -w1) : (ci == c1 ? w1 : 0.f);
                             row += up0 ? (double)t0 : 0.0;
                             row += up1 ? (double)t1 : 0.0;
                         }
-                        rs[j] = row;
+                        rs[jj] = row;
                     }
-                    double v = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+                    if constexpr (RPL == 4) v = (rs[0] + rs[1]) + (rs[2] + rs[3]);
+                    else if constexpr (RPL == 2) v = rs[0] + rs[1];
+                    else v = rs[0];
+                }
+                if constexpr (RPL < 4) {
+                    // the quad's partial sums meet in LDS; wave g = 0 folds them
+                    part[(ws * G + g) * 64 + lane] = v;
+                    __syncthreads();
+                    if (g == 0 && slice < S) {
+                        const double* pp = part + ws * G * 64 + lane;
+                        if constexpr (RPL == 2) v = pp[0] + pp[64];
+                        else v = (pp[0] + pp[64]) + (pp[128] + pp[192]);
+                    }
+                }
+                if (g == 0 && slice < S) {
                     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-                    if (lane == 0) red[wave] = v;
+                    if (lane == 0) red[ws] = v;
                 }
                 __syncthreads();
                 if (threadIdx.x == 0)
-                    for (int w = 0; w < W && k * W + w < S; ++w) tree.push(red[w]);
+                    for (int w = 0; w < WS && k * WS + w < S; ++w) tree.push(red[w]);
                 __syncthreads();
             }
             if (threadIdx.x == 0) {
@@ -345,11 +396,13 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 int8_t* bc = a.best_colour + (int64_t)r * a.n_total + off;
 #pragma unroll
                 for (int k = 0; k < MS; ++k) {
-                    const int slice = wave + k * W;
+                    const int slice = ws + k * WS;
                     const int m = slice * 64 + lane;
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (slice < S && 4 * m + j < n) bc[4 * m + j] = (int8_t)col8[j * plane + m];
+                    for (int jj = 0; jj < RPL; ++jj) {
+                        const int i = 4 * m + j0 + jj;
+                        if (slice < S && i < n) bc[i] = (int8_t)col8[(j0 + jj) * plane + m];
+                    }
                 }
             }
             __syncthreads();
@@ -359,14 +412,14 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     // ---- final phases ----
 #pragma unroll
     for (int k = 0; k < MS; ++k) {
-        const int slice = wave + k * W;
+        const int slice = ws + k * WS;
         const int m = slice * 64 + lane;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int i = 4 * m + j;
+        for (int jj = 0; jj < RPL; ++jj) {
+            const int i = 4 * m + j0 + jj;
             if (slice < S && i < n) {
-                th[i] = theta_from_phase(ph[k][j]);
-                if (pw) pw[i] = ph[k][j];
+                th[i] = theta_from_phase(ph[k][jj]);
+                if (pw) pw[i] = ph[k][jj];
             }
         }
     }
@@ -379,20 +432,25 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
 using KernelFn = void (*)(PersistArgs);
 
 struct Variant {
-    int tb, ms;
+    int tb, ms, rpl;
     KernelFn fn[3];  // QM = 0 (generic), 2, 3
+    // slices covered: (waves / waves per slice) x slices per wave group
+    int covers() const { return (tb / 64) / (4 / rpl) * ms; }
 };
 
-#define OIM_VARIANT(TB, MS)                                                              \
-    Variant {                                                                            \
-        TB, MS, {                                                                        \
-            persistent_sparse_kernel<TB, MS, 0>, persistent_sparse_kernel<TB, MS, 2>,    \
-                persistent_sparse_kernel<TB, MS, 3>                                      \
-        }                                                                                \
+#define OIM_VARIANT_R(TB, MS, RPL)                                                         \
+    Variant {                                                                              \
+        TB, MS, RPL, {                                                                     \
+            persistent_sparse_kernel<TB, MS, 0, RPL>, persistent_sparse_kernel<TB, MS, 2, RPL>, \
+                persistent_sparse_kernel<TB, MS, 3, RPL>                                   \
+        }                                                                                  \
     }
+#define OIM_VARIANT(TB, MS) OIM_VARIANT_R(TB, MS, 4)
 
 // Block sizes from one wave up: the small ones suit batches of small
-// instances (fewer idle lanes, cheap barriers); the autotuner times them all.
+// instances (fewer idle lanes, cheap barriers); the split-row shapes (last
+// rows) suit instances of a few slices with long rows.  The autotuner times
+// them all.
 const Variant kVariants[] = {
     OIM_VARIANT(64, 1),   OIM_VARIANT(64, 2),   OIM_VARIANT(64, 3),   OIM_VARIANT(64, 4),
     OIM_VARIANT(64, 6),   OIM_VARIANT(64, 8),
@@ -405,14 +463,18 @@ const Variant kVariants[] = {
     OIM_VARIANT(640, 4),  OIM_VARIANT(768, 3),  OIM_VARIANT(768, 4),
     OIM_VARIANT(1024, 1), OIM_VARIANT(1024, 2), OIM_VARIANT(1024, 3), OIM_VARIANT(1024, 4),
     OIM_VARIANT(1024, 5),
+    OIM_VARIANT_R(256, 1, 1),  OIM_VARIANT_R(256, 1, 2),  OIM_VARIANT_R(512, 1, 1),
+    OIM_VARIANT_R(512, 1, 2),  OIM_VARIANT_R(512, 2, 2),  OIM_VARIANT_R(1024, 1, 1),
+    OIM_VARIANT_R(1024, 2, 1), OIM_VARIANT_R(1024, 1, 2), OIM_VARIANT_R(1024, 2, 2),
 };
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
-size_t lds_bytes(int plane, int tb) {
+size_t lds_bytes(int plane, int tb, int rpl) {
     size_t b = (size_t)8 * 4 * plane;                 // (sin, cos) table
     b += ((size_t)4 * plane + 15) & ~(size_t)15;      // colours for readout
     b += sizeof(double) * (tb / 64 + kSliceTreeLevels) + 16;  // reduction, tree levels, flag
+    if (rpl < 4) b += sizeof(double) * (size_t)tb;    // quads' partial row sums (readout)
     return b;
 }
 
@@ -425,6 +487,7 @@ const Variant* pick_variant(int S, int tb_hint) {
     const Variant* best = nullptr;
     for (const Variant& v : kVariants) {
         const int W = v.tb / 64;
+        if (v.rpl != 4) continue;
         if (tb_hint ? v.tb != tb_hint : v.tb < 256) continue;
         if (W * v.ms < S) continue;
         if (!best) { best = &v; continue; }
@@ -441,10 +504,16 @@ int env_int(const char* name, int dflt) {
     return v ? atoi(v) : dflt;
 }
 
-const Variant* find_variant(int tb, int ms) {
+const Variant* find_variant(int tb, int ms, int rpl) {
     for (const Variant& v : kVariants)
-        if (v.tb == tb && v.ms == ms) return &v;
+        if (v.tb == tb && v.ms == ms && v.rpl == rpl) return &v;
     return nullptr;
+}
+
+// The variant covers every slice of the largest instance and its LDS fits.
+bool variant_ok(const Problem* p, const Variant& v) {
+    return v.covers() >= p->max_slices &&
+           lds_bytes(p->max_slices * 64, v.tb, v.rpl) <= kLdsLimit;
 }
 
 int q_class(int q) { return q == 2 ? 1 : q == 3 ? 2 : 0; }
@@ -454,8 +523,8 @@ int q_class(int q) { return q == 2 ? 1 : q == 3 ? 2 : 0; }
 const Variant* run_variant(const Problem* p, int q) {
     const int qc = q_class(q);
     if (p->tuned_tb[qc]) {
-        const Variant* v = find_variant(p->tuned_tb[qc], p->tuned_ms[qc]);
-        if (v) return v;
+        const Variant* v = find_variant(p->tuned_tb[qc], p->tuned_ms[qc], p->tuned_rpl[qc]);
+        if (v && variant_ok(p, *v)) return v;
     }
     const Variant* v = pick_variant(p->max_slices, env_int("OIM_PERSIST_TB", 0));
     return v ? v : pick_variant(p->max_slices, 0);
@@ -463,14 +532,14 @@ const Variant* run_variant(const Problem* p, int q) {
 
 }  // namespace
 
-bool persistent_variant_fits(const Problem* p, int tb, int ms) {
-    const Variant* v = find_variant(tb, ms);
-    return v && (tb / 64) * ms >= p->max_slices;
+bool persistent_variant_fits(const Problem* p, int tb, int ms, int rpl) {
+    const Variant* v = find_variant(tb, ms, rpl);
+    return v && variant_ok(p, *v);
 }
 
 bool persistent_sparse_fits(const Problem* p) {
     if (p->dense || p->max_slices == 0) return false;
-    if (lds_bytes(p->max_slices * 64, 1024) > kLdsLimit) return false;
+    if (lds_bytes(p->max_slices * 64, 1024, 4) > kLdsLimit) return false;
     if ((uint64_t)p->sell_entries * 8 > kMaxSellBytes) return false;
     return pick_variant(p->max_slices, 0) != nullptr;
 }
@@ -484,7 +553,7 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
                    const Variant* forced, int32_t sched_stride) {
     const int S = p->max_slices;
     const Variant* v = forced ? forced : run_variant(p, cfg->q);
-    if (!v || !persistent_sparse_fits(p))
+    if (!v || !persistent_sparse_fits(p) || !variant_ok(p, *v))
         return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
     PersistArgs a{};
     a.sell = reinterpret_cast<const int4*>(p->d_sell);
@@ -514,7 +583,7 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
     a.sched_stride = sched_stride;
     const int qi = cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0;
     KernelFn fn = v->fn[qi];
-    const size_t lds = lds_bytes(plane, v->tb);
+    const size_t lds = lds_bytes(plane, v->tb, v->rpl);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");
@@ -592,7 +661,7 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
     int tried = 0;
     for (const Variant& v : kVariants) {
         if (st) break;
-        if ((v.tb / 64) * v.ms < p->max_slices) continue;
+        if (!variant_ok(p, v)) continue;
         float t[2] = {0.f, 0.f};
         time_variant(v, trial_steps, 2, t);
         if (st) break;
@@ -600,6 +669,7 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
         if (rep && tried < OIM_TUNE_MAX) {
             rep->block[tried] = v.tb;
             rep->slices_per_wave[tried] = v.ms;
+            rep->rows_per_lane[tried] = v.rpl;
             rep->ms[tried] = t_min;
         }
         ++tried;
@@ -641,10 +711,12 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
     const int qc = q_class(cfg->q);
     p->tuned_tb[qc] = (int16_t)best->tb;
     p->tuned_ms[qc] = (int16_t)best->ms;
+    p->tuned_rpl[qc] = (int16_t)best->rpl;
     if (rep) {
         rep->n_tried = tried < OIM_TUNE_MAX ? tried : OIM_TUNE_MAX;
         rep->chosen_block = best->tb;
         rep->chosen_slices_per_wave = best->ms;
+        rep->chosen_rows_per_lane = best->rpl;
         rep->chosen_ms = best_ms;
     }
     return OIM_OK;

@@ -50,13 +50,15 @@ def tuned(problem, theta, K, Ks, sigma, seeds, *, q, dt, trial_steps=None, retun
     cache = _load(path)
     if not retune and key in cache:
         e = cache[key]
-        oim_set_tuning(problem.handle, q, e["block"], e["slices_per_wave"])
+        oim_set_tuning(problem.handle, q, e["block"], e["slices_per_wave"],
+                       e.get("rows_per_lane", 4))
         return e, False
     steps = int(K.shape[0])
     ts = trial_steps or max(1, min(steps, 500))
     rep = oim_autotune(problem.handle, problem.n, theta, K, Ks, sigma, seeds, q=q, dt=dt,
                        trial_steps=ts)
-    e = {"block": rep["block"], "slices_per_wave": rep["slices_per_wave"], "trial_ms": rep["ms"],
+    e = {"block": rep["block"], "slices_per_wave": rep["slices_per_wave"],
+         "rows_per_lane": rep["rows_per_lane"], "trial_ms": rep["ms"],
          "trial_steps": ts, "tried": rep["tried"]}
     cache[key] = e
     try:

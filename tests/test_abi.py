@@ -37,7 +37,7 @@ def test_every_declared_symbol_is_exported(oim):
 
 def test_abi_version_and_status_names(oim):
     from paper_2505_22631_amd import _lib
-    assert oim.oim_abi_version() == 1
+    assert oim.oim_abi_version() == 2
     assert _lib.status_name(0) == "OIM_OK"
     assert _lib.status_name(3) == "OIM_E_ASYM"
     assert _lib.status_name(99) == "OIM_E_UNKNOWN"

@@ -62,6 +62,47 @@ def test_every_variant_gives_identical_bits(oim):
     prob.close()
 
 
+@pytest.mark.parametrize("q", [2, 3, 5])
+def test_split_row_variants_give_identical_bits(oim, q):
+    # few slices and long rows (the G(800, 0.06) shape, degree ~48, and a
+    # ragged tail): every launch variant, whole-quad and split-row, gives the
+    # same phases and the same in-run readouts (trace, best, colours)
+    import torch
+    g = synth.erdos_renyi(800, 0.06, seed=0)
+    J = (-g.w).astype(np.float32)
+    g2 = synth.gnp_avg_degree(301, 30.0, seed=4, signed=True)
+    big, off = synth.block_diagonal([g, g2])
+    Jb = (-big.w).astype(np.float32)
+    R, steps = 3, 90
+    with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, Jb, off) as prob:
+        kmax = 4 * 0.5 / (DT * prob.info["max_abs_row_sum"])
+        K = torch.from_numpy(synth.ramp(0.0, kmax, steps)).cuda()
+        Ks = torch.from_numpy(synth.ramp(0.0, 0.5 / (DT * q), steps)).cuda()
+        sg = torch.from_numpy(synth.const(0.1, steps)).cuda()
+        sd = torch.from_numpy(synth.seeds(R, 3)).cuda()
+        th0 = torch.from_numpy(synth.theta0(R, big.n, seed=1)).cuda()
+        outs = {}
+        for block in (256, 512, 1024):
+            for spw in (1, 2, 3, 4, 5, 6, 8):
+                for rpl in (4, 2, 1):
+                    try:
+                        oim.oim_set_tuning(prob.handle, q, block, spw, rpl)
+                    except oim.OimError:
+                        continue
+                    th = th0.clone()
+                    ro = oim.run(prob, th, K, Ks, sg, sd, q=q, dt=DT, readout_every=30,
+                                 want_best=True)
+                    outs[(block, spw, rpl)] = (th.cpu().numpy(),
+                                               {k: v.cpu().numpy() for k, v in ro.items()})
+    assert any(k[2] == 1 for k in outs) and any(k[2] == 2 for k in outs)
+    ref_th, ref_ro = outs[next(k for k in outs if k[2] == 4)]
+    for k, (th, ro) in outs.items():
+        np.testing.assert_array_equal(th, ref_th, err_msg=f"variant {k}")
+        for name in ("trace", "best_h", "best_step", "best_colour"):
+            np.testing.assert_array_equal(ro[name], ref_ro[name], err_msg=f"variant {k} {name}")
+    print(f"q={q}: {len(outs)} variants identical", flush=True)
+
+
 def test_autotune_keeps_a_variant_and_leaves_theta(oim):
     import torch
     graphs = [synth.planted_colouring(nv, 4.6, 3, seed=nv)[0] for nv in (150, 400, 600)]
@@ -72,11 +113,12 @@ def test_autotune_keeps_a_variant_and_leaves_theta(oim):
     torch.cuda.synchronize()
     assert torch.equal(th0, before)
     assert len(rep["tried"]) >= 5
-    assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in rep["tried"]]
+    win = (rep["block"], rep["slices_per_wave"], rep["rows_per_lane"])
+    assert win in [(b, s, r) for b, s, r, _ in rep["tried"]]
     # the winner comes from the four fastest of the first pass; its reported
     # time is its median in the final pass (trials twice as long)
-    fastest = sorted(rep["tried"], key=lambda t: t[2])[:4]
-    assert (rep["block"], rep["slices_per_wave"]) in [(b, s) for b, s, _ in fastest]
+    fastest = sorted(rep["tried"], key=lambda t: t[3])[:4]
+    assert win in [(b, s, r) for b, s, r, _ in fastest]
     assert rep["ms"] > 0
     got, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
     np.testing.assert_array_equal(got, ref)
@@ -96,7 +138,9 @@ def test_tune_cache_roundtrip(oim, tmp_path, monkeypatch):
     assert measured1
     prob2, *_ = _setup(oim, graphs, 2, 200, 3, seed=5)
     e2, measured2 = tune.tuned(prob2, th0, K, Ks, sg, sd, q=3, dt=DT)
-    assert not measured2 and (e2["block"], e2["slices_per_wave"]) == (e1["block"], e1["slices_per_wave"])
+    assert not measured2
+    assert (e2["block"], e2["slices_per_wave"], e2["rows_per_lane"]) == \
+        (e1["block"], e1["slices_per_wave"], e1["rows_per_lane"])
     ref, _ = _run(oim, prob, th0, K, Ks, sg, sd, 3)
     got, _ = _run(oim, prob2, th0, K, Ks, sg, sd, 3)
     np.testing.assert_array_equal(got, ref)
