@@ -174,4 +174,4 @@ def test_tuning_entry_points_reject_bad_handles(oim):
     rep = _lib.TuneReport()
     assert L.oim_autotune(None, ctypes.byref(cfg), None, None, None, None, None, 5,
                           ctypes.byref(rep), None) == 8
-    assert L.oim_set_tuning(None, 2, 64, 1) == 8
+    assert L.oim_set_tuning(None, 2, 64, 1, 4) == 8
