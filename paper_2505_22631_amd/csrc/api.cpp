@@ -242,14 +242,15 @@ __attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
     return OIM_OK;
 }
 
-__attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_cfg* cfg,
-                                                   const float* K, const float* Ks,
-                                                   const float* sigma, const uint64_t* seeds,
-                                                   int64_t step0, float* theta, uint32_t* phase,
-                                                   const oim_readout* ro, hipStream_t stream) {
-    clear_error();
-    Problem* p = checked(h);
-    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+}  // extern "C"
+
+namespace oim {
+
+// Argument checks of oim_run and of its allocation-free variant, before any
+// device work.
+int run_common_checks(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                      const float* sigma, const uint64_t* seeds, int64_t step0,
+                      const float* theta, const oim_readout* ro) {
     int st = validate_cfg(p, cfg);
     if (st) return st;
     if (!theta || !seeds) return set_error(OIM_E_ARG, "theta or seeds is NULL");
@@ -259,18 +260,37 @@ __attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_
         return set_error(OIM_E_ARG, "global step index must stay below 2^32");
     if (ro && cfg->readout_every == 0 && (ro->trace || ro->best_h || ro->best_step || ro->best_colour))
         return set_error(OIM_E_ARG, "readout buffers given with readout_every = 0");
-    if ((st = check_device(p))) return st;
+    const uint32_t loop = cfg->flags & OIM_LOOP_MASK;
+    if (p->dense && loop == OIM_LOOP_PERSISTENT)
+        return set_error(OIM_E_UNSUPPORTED, "dense problems run stepwise");
+    if (!p->dense && p->n_inst > 1 && (loop == OIM_LOOP_STEPWISE || !persistent_sparse_fits(p)))
+        return set_error(OIM_E_UNSUPPORTED, "block-diagonal batches run on the LDS-resident loop only");
+    if (!p->dense && loop == OIM_LOOP_PERSISTENT && !persistent_sparse_fits(p))
+        return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != p->device)
+        return set_error(OIM_E_STATE, "problem belongs to another device");
+    return OIM_OK;
+}
+
+}  // namespace oim
+
+extern "C" {
+
+__attribute__((visibility("default"))) int oim_run(oim_problem h, const oim_run_cfg* cfg,
+                                                   const float* K, const float* Ks,
+                                                   const float* sigma, const uint64_t* seeds,
+                                                   int64_t step0, float* theta, uint32_t* phase,
+                                                   const oim_readout* ro, hipStream_t stream) {
+    clear_error();
+    Problem* p = checked(h);
+    if (!p) return set_error(OIM_E_STATE, "invalid or destroyed problem");
+    int st = run_common_checks(p, cfg, K, Ks, sigma, seeds, step0, theta, ro);
+    if (st) return st;
     if (cfg->steps == 0) return OIM_OK;  // nothing to integrate; theta untouched
     const uint32_t loop = cfg->flags & OIM_LOOP_MASK;
-    if (p->dense) {
-        if (loop == OIM_LOOP_PERSISTENT)
-            return set_error(OIM_E_UNSUPPORTED, "dense problems run stepwise");
-        return launch_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
-    }
-    const bool fits = persistent_sparse_fits(p);
-    if (p->n_inst > 1 && (loop == OIM_LOOP_STEPWISE || !fits))
-        return set_error(OIM_E_UNSUPPORTED, "block-diagonal batches run on the LDS-resident loop only");
-    if (loop == OIM_LOOP_PERSISTENT || (loop == OIM_LOOP_AUTO && fits))
+    if (p->dense) return launch_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);
+    if (loop == OIM_LOOP_PERSISTENT || (loop == OIM_LOOP_AUTO && persistent_sparse_fits(p)))
         return launch_persistent_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro,
                                         stream);
     return launch_stepwise_sparse(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream);

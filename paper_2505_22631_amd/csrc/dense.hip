@@ -695,37 +695,28 @@ void dense_release(Problem* p) {
     p->d_Jtiled32 = nullptr;
 }
 
-int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
-                 const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
-                 uint32_t* phase, const oim_readout* ro, hipStream_t stream) {
+namespace {
+
+// Workspace of one run: U (4 B) + two X sets (8 B each: 4 x BF16 or 2 x FP32)
+// per (replica, row) slot, then the readout scratch H[R], best tmp [R]
+// (FP64) and best step [R].
+size_t dense_need(int n, int R) {
+    const int np = (n + kTM - 1) / kTM * kTM;
+    const int Rp = (R + kTR - 1) / kTR * kTR;
+    const size_t plane = (size_t)Rp * np;
+    return plane * 4 + 2 * 4 * plane * 2 + (size_t)R * 8 * 2 + (size_t)R * 4 + 256;
+}
+
+int run_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+              const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+              uint32_t* phase, const oim_readout* ro, hipStream_t stream, void* work) {
     const bool fp32 = (cfg->flags & OIM_PREC_MASK) == OIM_PREC_FP32;
     const int n = p->n, R = cfg->R;
     const int np = (n + kTM - 1) / kTM * kTM;
-    if (fp32 && !p->d_Jtiled32) {
-        // the FP32 image of J, made once per problem on the caller's stream
-        int st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jtiled32),
-                               (size_t)np * np * sizeof(float), "FP32 tiled J");
-        if (st) return st;
-        hipLaunchKernelGGL(dense_tile32_kernel, dim3(4096), dim3(256), 0, stream, p->d_Jdense,
-                           p->d_Jtiled32, n, np);
-        if ((st = check_launch("dense_tile32_kernel"))) return st;
-    }
     const int Rp = (R + kTR - 1) / kTR * kTR;
     const size_t plane = (size_t)Rp * np;
     const int M = cfg->readout_every;
-    const int nread = M > 0 ? (cfg->steps + M - 1) / M : 0;
-    // workspace: U (4 B) + two X sets (8 B each: 4 x BF16 or 2 x FP32) per slot, then readout
-    // scratch: H[R], best tmp [R] (f64), best step [R]
-    const size_t need = plane * 4 + 2 * 4 * plane * 2 + (size_t)R * 8 * 2 + (size_t)R * 4 + 256;
-    if (p->work_bytes < need) {
-        hipFree(p->d_work);
-        p->d_work = nullptr;
-        p->work_bytes = 0;
-        int st = alloc_or_fail(&p->d_work, need, "dense workspace");
-        if (st) return st;
-        p->work_bytes = need;
-    }
-    unsigned char* w = static_cast<unsigned char*>(p->d_work);
+    unsigned char* w = static_cast<unsigned char*>(work);
     uint32_t* U = reinterpret_cast<uint32_t*>(w);
     unsigned char* X0 = w + plane * 4;
     unsigned char* X1 = X0 + 4 * plane * 2;
@@ -786,7 +777,7 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
             if ((st = check_launch("dense_best_kernel"))) return st;
         }
     }
-    (void)nread;
+
     if (ro && M > 0 && cfg->steps > 0) {
         if (ro->best_h) {
             e = hipMemcpyAsync(ro->best_h, btmp, sizeof(double) * R, hipMemcpyDeviceToDevice, stream);
@@ -799,6 +790,49 @@ int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     }
     hipLaunchKernelGGL(dense_final_kernel, dim3(2048), dim3(256), 0, stream, U, theta, phase, n, R, np);
     return check_launch("dense_final_kernel");
+}
+
+}  // namespace
+
+size_t dense_workspace_bytes(const Problem* p, const oim_run_cfg* cfg) {
+    return dense_need(p->n, cfg->R);
+}
+
+int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                 const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                 uint32_t* phase, const oim_readout* ro, hipStream_t stream) {
+    const bool fp32 = (cfg->flags & OIM_PREC_MASK) == OIM_PREC_FP32;
+    const int n = p->n;
+    const int np = (n + kTM - 1) / kTM * kTM;
+    if (fp32 && !p->d_Jtiled32) {
+        // the FP32 image of J, made once per problem on the caller's stream
+        int st = alloc_or_fail(reinterpret_cast<void**>(&p->d_Jtiled32),
+                               (size_t)np * np * sizeof(float), "FP32 tiled J");
+        if (st) return st;
+        hipLaunchKernelGGL(dense_tile32_kernel, dim3(4096), dim3(256), 0, stream, p->d_Jdense,
+                           p->d_Jtiled32, n, np);
+        if ((st = check_launch("dense_tile32_kernel"))) return st;
+    }
+    const size_t need = dense_workspace_bytes(p, cfg);
+    if (p->work_bytes < need) {
+        (void)hipFree(p->d_work);
+        p->d_work = nullptr;
+        p->work_bytes = 0;
+        int st = alloc_or_fail(&p->d_work, need, "dense workspace");
+        if (st) return st;
+        p->work_bytes = need;
+    }
+    return run_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, p->d_work);
+}
+
+int launch_dense_ws(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                    const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                    uint32_t* phase, const oim_readout* ro, hipStream_t stream, void* work) {
+    const bool fp32 = (cfg->flags & OIM_PREC_MASK) == OIM_PREC_FP32;
+    if (fp32 && !p->d_Jtiled32)
+        return set_error(OIM_E_UNSUPPORTED,
+                         "the FP32 image of J is made by a first oim_run with OIM_PREC_FP32");
+    return run_dense(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, work);
 }
 
 }  // namespace oim

@@ -122,6 +122,19 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
                            float* theta, uint32_t* phase, const oim_readout* ro,
                            hipStream_t stream);
 void stepwise_release(Problem* p);
+size_t stepwise_workspace_bytes(const Problem* p, const oim_run_cfg* cfg);
+int launch_stepwise_sparse_ws(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                              const float* sigma, const uint64_t* seeds, int64_t step0,
+                              float* theta, uint32_t* phase, const oim_readout* ro,
+                              hipStream_t stream, void* work);
+size_t dense_workspace_bytes(const Problem* p, const oim_run_cfg* cfg);
+int launch_dense_ws(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                    const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                    uint32_t* phase, const oim_readout* ro, hipStream_t stream, void* work);
+// checks of oim_run shared with its allocation-free variant (api.cpp)
+int run_common_checks(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                      const float* sigma, const uint64_t* seeds, int64_t step0,
+                      const float* theta, const oim_readout* ro);
 int launch_dense(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
                  const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
                  uint32_t* phase, const oim_readout* ro, hipStream_t stream);

@@ -316,41 +316,51 @@ void stepwise_release(Problem* p) {
     p->step_plans = nullptr;
 }
 
-int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
-                           const float* sigma, const uint64_t* seeds, int64_t step0,
-                           float* theta, uint32_t* phase, const oim_readout* ro,
-                           hipStream_t stream) {
-    const int n = p->n, R = cfg->R, steps = cfg->steps, M = cfg->readout_every;
-    const int Rp = (R + 63) / 64 * 64;
-    const int quads = (n + 3) / 4;
-    const int np = quads * 4;
-    const int gx = (quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
-    const size_t cells = (size_t)np * Rp;
+namespace {
+
+struct Shape {
+    int n, R, steps, M, Rp, quads, np, gx, chunk;
+    size_t cells, args_off, bytes;
+};
+
+Shape shape_of(const Problem* p, const oim_run_cfg* cfg) {
+    Shape sh{};
+    sh.n = p->n;
+    sh.R = cfg->R;
+    sh.steps = cfg->steps;
+    sh.M = cfg->readout_every;
+    sh.Rp = (sh.R + 63) / 64 * 64;
+    sh.quads = (sh.n + 3) / 4;
+    sh.np = sh.quads * 4;
+    sh.gx = (sh.quads + kQuadsPerBlock - 1) / kQuadsPerBlock;
+    sh.cells = (size_t)sh.np * sh.Rp;
     // chunk: a multiple of the readout period, about 64 steps
-    int chunk = std::min(steps, 64);
-    if (M > 0) chunk = std::max(1, (std::min(steps, std::max(64, M)) / M)) * M;
-    chunk = std::max(1, std::min(chunk, steps));
-    const size_t args_off = (cells * (4 + 8 + 8) + (size_t)gx * Rp * 8 + (size_t)R * 12 + 255) & ~(size_t)255;
-    const size_t need = args_off + 256;
-    if (p->work_bytes < need) {
-        clear_plans(p);  // they were captured on the old workspace
-        (void)hipFree(p->d_work);
-        p->d_work = nullptr;
-        p->work_bytes = 0;
-        hipError_t e = hipMalloc(&p->d_work, need);
-        if (e != hipSuccess) {
-            p->d_work = nullptr;
-            return e == hipErrorOutOfMemory ? set_error(OIM_E_NOMEM, "stepwise workspace")
-                                            : hip_error(e, "hipMalloc stepwise workspace");
-        }
-        p->work_bytes = need;
-    }
-    if (!p->step_plans) {
+    int chunk = std::min(sh.steps, 64);
+    if (sh.M > 0) chunk = std::max(1, (std::min(sh.steps, std::max(64, sh.M)) / sh.M)) * sh.M;
+    sh.chunk = std::max(1, std::min(chunk, sh.steps));
+    sh.args_off = (sh.cells * (4 + 8 + 8) + (size_t)sh.gx * sh.Rp * 8 + (size_t)sh.R * 12 + 255) &
+                  ~(size_t)255;
+    sh.bytes = sh.args_off + 256;
+    return sh;
+}
+
+// The stepwise loop on a workspace of at least stepwise_workspace_bytes:
+// with `graph`, the chunk of steps comes from the problem's plan cache
+// (captured on first use) and is replayed; without, the same kernels are
+// launched one by one on the stream (no capture, no allocation).
+int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                 const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                 uint32_t* phase, const oim_readout* ro, hipStream_t stream, void* work,
+                 bool graph) {
+    const Shape sh = shape_of(p, cfg);
+    const int n = sh.n, R = sh.R, steps = sh.steps, M = sh.M, Rp = sh.Rp, np = sh.np, gx = sh.gx;
+    const int chunk = sh.chunk;
+    const size_t cells = sh.cells, args_off = sh.args_off;
+    if (graph && !p->step_plans) {
         p->step_plans = new (std::nothrow) PlanCache();
         if (!p->step_plans) return set_error(OIM_E_NOMEM, "plan cache");
     }
-    PlanCache& cache = *static_cast<PlanCache*>(p->step_plans);
-    unsigned char* w = static_cast<unsigned char*>(p->d_work);
+    unsigned char* w = static_cast<unsigned char*>(work);
     uint32_t* U = reinterpret_cast<uint32_t*>(w);
     float2* T0 = reinterpret_cast<float2*>(w + cells * 4);
     float2* T1 = T0 + cells;
@@ -432,72 +442,77 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     };
 
     const bool flip = (chunk & 1) != 0;
-    Plan* plan = nullptr;
-    for (int i = 0; i < cache.count; ++i) {
-        Plan& c = cache.plans[i];
-        if (c.q == cfg->q && c.R == R && c.M == M && c.chunk == chunk && c.work == p->d_work) {
-            plan = &c;
-            break;
-        }
-    }
+    const int replays = (steps + chunk - 1) / chunk;
     hipError_t e = hipSuccess;
-    if (!plan) {
-        // capture a new plan, evicting the least recently used one if full
-        int slot = cache.count;
-        if (cache.count == PlanCache::kMax) {
-            slot = 0;
-            for (int i = 1; i < cache.count; ++i)
-                if (cache.plans[i].last_use < cache.plans[slot].last_use) slot = i;
-            destroy_plan(cache.plans[slot]);
-        } else {
-            ++cache.count;
-        }
-        Plan& pl = cache.plans[slot];
-        pl = Plan{};
-        hipStream_t cap = nullptr;
-        e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
-        if (e != hipSuccess) st = hip_error(e, "capture stream");
-        for (int par = 0; par < (flip ? 2 : 1) && !st; ++par) {
-            e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) {
-                st = hip_error(e, "hipStreamBeginCapture");
+    if (!graph) {
+        for (int c = 0; c < replays; ++c)
+            if ((st = record_chunk(stream, flip && (c & 1)))) return st;
+    } else {
+        PlanCache& cache = *static_cast<PlanCache*>(p->step_plans);
+        Plan* plan = nullptr;
+        for (int i = 0; i < cache.count; ++i) {
+            Plan& c = cache.plans[i];
+            if (c.q == cfg->q && c.R == R && c.M == M && c.chunk == chunk && c.work == work) {
+                plan = &c;
                 break;
             }
-            st = record_chunk(cap, par == 1);
-            e = hipStreamEndCapture(cap, &pl.g[par]);
-            if (!st && e != hipSuccess) st = hip_error(e, "hipStreamEndCapture");
-            if (!st && (e = hipGraphInstantiate(&pl.x[par], pl.g[par], nullptr, nullptr, 0)) != hipSuccess)
-                st = hip_error(e, "hipGraphInstantiate");
         }
-        if (cap) (void)hipStreamDestroy(cap);
-        if (!st && (e = hipEventCreateWithFlags(&pl.done, hipEventDisableTiming)) != hipSuccess)
-            st = hip_error(e, "plan event");
-        if (st) {
-            destroy_plan(pl);
-            // keep the cache dense: move the last plan into the freed slot
-            if (slot != cache.count - 1) {
-                pl = cache.plans[cache.count - 1];
-                cache.plans[cache.count - 1] = Plan{};
+        if (!plan) {
+            // capture a new plan, evicting the least recently used one if full
+            int slot = cache.count;
+            if (cache.count == PlanCache::kMax) {
+                slot = 0;
+                for (int i = 1; i < cache.count; ++i)
+                    if (cache.plans[i].last_use < cache.plans[slot].last_use) slot = i;
+                destroy_plan(cache.plans[slot]);
+            } else {
+                ++cache.count;
             }
-            --cache.count;
-            return st;
+            Plan& pl = cache.plans[slot];
+            pl = Plan{};
+            hipStream_t cap = nullptr;
+            e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+            if (e != hipSuccess) st = hip_error(e, "capture stream");
+            for (int par = 0; par < (flip ? 2 : 1) && !st; ++par) {
+                e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+                if (e != hipSuccess) {
+                    st = hip_error(e, "hipStreamBeginCapture");
+                    break;
+                }
+                st = record_chunk(cap, par == 1);
+                e = hipStreamEndCapture(cap, &pl.g[par]);
+                if (!st && e != hipSuccess) st = hip_error(e, "hipStreamEndCapture");
+                if (!st && (e = hipGraphInstantiate(&pl.x[par], pl.g[par], nullptr, nullptr, 0)) != hipSuccess)
+                    st = hip_error(e, "hipGraphInstantiate");
+            }
+            if (cap) (void)hipStreamDestroy(cap);
+            if (!st && (e = hipEventCreateWithFlags(&pl.done, hipEventDisableTiming)) != hipSuccess)
+                st = hip_error(e, "plan event");
+            if (st) {
+                destroy_plan(pl);
+                // keep the cache dense: move the last plan into the freed slot
+                if (slot != cache.count - 1) {
+                    pl = cache.plans[cache.count - 1];
+                    cache.plans[cache.count - 1] = Plan{};
+                }
+                --cache.count;
+                return st;
+            }
+            pl.q = cfg->q;
+            pl.R = R;
+            pl.M = M;
+            pl.chunk = chunk;
+            pl.work = work;
+            plan = &pl;
         }
-        pl.q = cfg->q;
-        pl.R = R;
-        pl.M = M;
-        pl.chunk = chunk;
-        pl.work = p->d_work;
-        plan = &pl;
+        plan->last_use = ++cache.clock;
+        for (int c = 0; c < replays; ++c) {
+            e = hipGraphLaunch(plan->x[flip ? (c & 1) : 0], stream);
+            if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
+        }
+        e = hipEventRecord(plan->done, stream);
+        if (e != hipSuccess) return hip_error(e, "plan event record");
     }
-    plan->last_use = ++cache.clock;
-
-    const int replays = (steps + chunk - 1) / chunk;
-    for (int c = 0; c < replays; ++c) {
-        e = hipGraphLaunch(plan->x[flip ? (c & 1) : 0], stream);
-        if (e != hipSuccess) return hip_error(e, "hipGraphLaunch");
-    }
-    e = hipEventRecord(plan->done, stream);
-    if (e != hipSuccess) return hip_error(e, "plan event record");
     // readout after the last step when steps is not a multiple of M
     if (M > 0 && steps % M != 0) {
         ReadArgs rl = ra;
@@ -521,6 +536,42 @@ int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, c
     }
     hipLaunchKernelGGL(stepwise_final_kernel, dim3(2048), dim3(256), 0, stream, U, theta, phase, n, R, Rp);
     return check_launch("stepwise_final_kernel");
+}
+
+}  // namespace
+
+size_t stepwise_workspace_bytes(const Problem* p, const oim_run_cfg* cfg) {
+    return shape_of(p, cfg).bytes;
+}
+
+int launch_stepwise_sparse(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                           const float* sigma, const uint64_t* seeds, int64_t step0,
+                           float* theta, uint32_t* phase, const oim_readout* ro,
+                           hipStream_t stream) {
+    const size_t need = stepwise_workspace_bytes(p, cfg);
+    if (p->work_bytes < need) {
+        clear_plans(p);  // they were captured on the old workspace
+        (void)hipFree(p->d_work);
+        p->d_work = nullptr;
+        p->work_bytes = 0;
+        hipError_t e = hipMalloc(&p->d_work, need);
+        if (e != hipSuccess) {
+            p->d_work = nullptr;
+            return e == hipErrorOutOfMemory ? set_error(OIM_E_NOMEM, "stepwise workspace")
+                                            : hip_error(e, "hipMalloc stepwise workspace");
+        }
+        p->work_bytes = need;
+    }
+    return run_stepwise(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, p->d_work,
+                        true);
+}
+
+int launch_stepwise_sparse_ws(Problem* p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                              const float* sigma, const uint64_t* seeds, int64_t step0,
+                              float* theta, uint32_t* phase, const oim_readout* ro,
+                              hipStream_t stream, void* work) {
+    return run_stepwise(p, cfg, K, Ks, sigma, seeds, step0, theta, phase, ro, stream, work,
+                        false);
 }
 
 }  // namespace oim
