@@ -55,6 +55,13 @@ def lib():
         L.orc_run_dense.argtypes = [_i32, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P, _P,
                                     _i32]
         L.orc_run_dense.restype = ctypes.c_int
+        L.orc_run_dense_bf16x3.argtypes = [_i32, _P, _i32, _i32, _i32, _i64, _f64, _P, _P, _P, _P,
+                                           _P, _i32]
+        L.orc_run_dense_bf16x3.restype = ctypes.c_int
+        L.orc_coupling_dense_bf16x3.argtypes = [_i32, _P, _P, _P]
+        L.orc_coupling_dense_bf16x3.restype = None
+        L.orc_bf16_round.argtypes = [ctypes.c_float]
+        L.orc_bf16_round.restype = ctypes.c_float
         L.orc_round_f32.argtypes = [_i64, _P, _i32, _P]
         L.orc_round_f32.restype = None
         L.orc_cut_int.argtypes = [_i32, _P, _P, _P, _P]
@@ -222,11 +229,19 @@ def relaxed_cut(row_ptr, col, J, theta):
     return float(np.sum(0.5 * w * (1.0 - np.cos(d))))
 
 
-def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
-    """Integrate Eq. 5 with the all-pairs (dense) coupling sum, diagonal ignored."""
+def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0, precision="fp64"):
+    """Integrate Eq. 5 with the all-pairs (dense) coupling sum, diagonal ignored.
+
+    precision "fp64": the direct sum of J_ij sin(th_i - th_j) in FP64.
+    precision "bf16x3": the coupling through sin(a - b) = sin a cos b - cos a sin b
+    with every GEMM operand split into two BF16 halves and the three products
+    J_hi X_hi + J_hi X_lo + J_lo X_hi (FP64 products and sums); the rest of the
+    step in FP64."""
     if np.ndim(K) == 2:
-        return _per_replica(lambda th, **k: run_dense(J, th, **k), theta0, K, Ks, sigma, seeds,
-                            q=q, dt=dt, step0=step0, nthreads=nthreads)
+        return _per_replica(lambda th, **k: run_dense(J, th, precision=precision, **k), theta0,
+                            K, Ks, sigma, seeds, q=q, dt=dt, step0=step0, nthreads=nthreads)
+    if precision not in ("fp64", "bf16x3"):
+        raise ValueError(f"unknown precision {precision!r}")
     Jd = _c(J, np.float64)
     th = np.array(theta0, dtype=np.float64, order="C", copy=True)
     if th.ndim == 1:
@@ -235,12 +250,31 @@ def run_dense(J, theta0, *, q, dt, K, Ks, sigma, seeds, step0=0, nthreads=0):
     assert Jd.shape == (n, n)
     steps = len(K)
     sd = _c(seeds, np.uint64)
-    rc = lib().orc_run_dense(n, _ptr(Jd), int(q), R, steps, int(step0), float(dt),
-                             _ptr(_sched(K, steps)), _ptr(_sched(Ks, steps)),
-                             _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th), int(nthreads))
+    fn = lib().orc_run_dense if precision == "fp64" else lib().orc_run_dense_bf16x3
+    rc = fn(n, _ptr(Jd), int(q), R, steps, int(step0), float(dt), _ptr(_sched(K, steps)),
+            _ptr(_sched(Ks, steps)), _ptr(_sched(sigma, steps)), _ptr(sd), _ptr(th),
+            int(nthreads))
     if rc != 0:
-        raise ValueError("orc_run_dense rejected its arguments")
+        raise ValueError("dense oracle run rejected its arguments")
     return th
+
+
+def coupling_dense_bf16x3(J, theta) -> np.ndarray:
+    """One coupling evaluation c_i of the BF16x3 split-product form (see
+    run_dense) for one phase vector; FP64 out."""
+    Jd = _c(J, np.float64)
+    th = _c(theta, np.float64)
+    n = th.shape[0]
+    assert Jd.shape == (n, n) and th.ndim == 1
+    out = np.zeros(n, np.float64)
+    lib().orc_coupling_dense_bf16x3(n, _ptr(Jd), _ptr(th), _ptr(out))
+    return out
+
+
+def bf16_round(x: float) -> float:
+    """BF16 rounding (to nearest, ties to even) of an FP32 value, as the
+    oracle's split uses it."""
+    return float(lib().orc_bf16_round(float(np.float32(x))))
 
 
 # -------------------------------------------------------------- readout ----

@@ -126,6 +126,84 @@ static void coupling_rows(int32_t i0, int32_t i1, int32_t n, const int64_t* row_
     }
 }
 
+/* ------------------------------------------------------------------------ */
+/* BF16x3 split products for a dense coupling (the precision of the dense   */
+/* all-to-all workload; the paper computes in FP32).  The coupling sum is    */
+/* taken through the identity sin(a - b) = sin a cos b - cos a sin b:        */
+/*   c_i = sin th_i * Y_C,i - cos th_i * Y_S,i,  Y_X,i = sum_{j != i} J_ij X_j */
+/* where every GEMM operand x (J_ij, and sin th_j / cos th_j rounded to      */
+/* FP32) is split as x = x_hi + x_lo + e, x_hi = bf16(x),                    */
+/* x_lo = bf16(x - x_hi), and each product J_ij X_j is replaced by           */
+/* J_hi X_hi + J_hi X_lo + J_lo X_hi (the J_lo X_lo term dropped).  Products */
+/* and sums here are FP64 in row order, so the only departures from the      */
+/* exact coupling are the splits and the dropped term:                       */
+/*   |c_i(bf16x3) - c_i| <= ~3 * 2^-16 * sum_j |J_ij|.                        */
+/* ------------------------------------------------------------------------ */
+/* BF16 of an FP32 value: the FP32 bit pattern rounded to its top 16 bits,  */
+/* to nearest, ties to even (finite inputs). */
+static float bf16_round(float x) {
+    uint32_t u;
+    memcpy(&u, &x, sizeof u);
+    const uint32_t keep_lsb = (u >> 16) & 1u;
+    u = (u + 0x7fffu + keep_lsb) & 0xffff0000u;
+    float r;
+    memcpy(&r, &u, sizeof r);
+    return r;
+}
+
+float orc_bf16_round(float x) { return bf16_round(x); }
+
+/* hi and lo halves of the split of one FP32 value (x - hi is exact in FP32) */
+static void split3(float x, double* hi, double* lo) {
+    const float h = bf16_round(x);
+    *hi = (double)h;
+    *lo = (double)bf16_round(x - h);
+}
+
+/* The split GEMM operands of the phases of rows i0 .. i1-1: xs holds four
+ * planes of n, (sin_hi, sin_lo, cos_hi, cos_lo). */
+static void split_x_rows(int32_t i0, int32_t i1, int32_t n, const double* th, double* xs) {
+    for (int32_t j = i0; j < i1; ++j) {
+        split3((float)sin(th[j]), &xs[j], &xs[n + j]);
+        split3((float)cos(th[j]), &xs[2 * n + j], &xs[3 * n + j]);
+    }
+}
+
+/* Coupling sums of rows i0 .. i1-1 from the split J (Jsp: n*n hi, then n*n
+ * lo, diagonal zero) and the split phases of every row. */
+static void coupling_rows_bf16x3(int32_t i0, int32_t i1, int32_t n, const double* Jsp,
+                                 const double* xs, const double* th, double* coup) {
+    const double* Jh = Jsp;
+    const double* Jl = Jsp + (size_t)n * n;
+    const double *sh = xs, *sl = xs + n, *ch = xs + 2 * n, *cl = xs + 3 * n;
+    for (int32_t i = i0; i < i1; ++i) {
+        double ys = 0.0, yc = 0.0;
+        for (int32_t j = 0; j < n; ++j) {
+            if (j == i) continue;
+            const double h = Jh[(int64_t)i * n + j], l = Jl[(int64_t)i * n + j];
+            ys += h * sh[j] + h * sl[j] + l * sh[j];
+            yc += h * ch[j] + h * cl[j] + l * ch[j];
+        }
+        coup[i] = sin(th[i]) * yc - cos(th[i]) * ys;
+    }
+}
+
+void orc_coupling_dense_bf16x3(int32_t n, const double* J, const double* theta, double* out) {
+    double* Jsp = (double*)malloc(sizeof(double) * 2 * (size_t)n * n);
+    double* xs = (double*)malloc(sizeof(double) * 4 * (size_t)n);
+    if (!Jsp || !xs) {
+        free(Jsp);
+        free(xs);
+        for (int32_t i = 0; i < n; ++i) out[i] = NAN;
+        return;
+    }
+    for (int64_t k = 0; k < (int64_t)n * n; ++k) split3((float)J[k], &Jsp[k], &Jsp[(size_t)n * n + k]);
+    split_x_rows(0, n, n, theta, xs);
+    coupling_rows_bf16x3(0, n, n, Jsp, xs, theta, out);
+    free(Jsp);
+    free(xs);
+}
+
 /* The update loop of Algorithm 1 for oscillators i0 .. i1-1: forward Euler
  * with the SHIL term and the noise kick, then the wrap into one period. */
 static void update_rows(int32_t i0, int32_t i1, int32_t q, double dt, double Kt, double Kst,
@@ -140,7 +218,7 @@ static void update_rows(int32_t i0, int32_t i1, int32_t q, double dt, double Kt,
 }
 
 static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, const double* Jv,
-                      const double* Jdense, int32_t q, int32_t R, int32_t steps, int64_t step0,
+                      const double* Jdense, const double* Jsplit, int32_t q, int32_t R, int32_t steps, int64_t step0,
                       double dt, const double* K, const double* Ks, const double* sigma,
                       const uint64_t* seeds, double* theta, int32_t nthreads, int32_t n_inst,
                       const int32_t* inst_off, uint32_t inst_base) {
@@ -170,13 +248,20 @@ static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, con
         for (int32_t r = 0; r < R; ++r) {
             double* th = theta + (int64_t)r * n;
             double* coup = (double*)malloc(sizeof(double) * (size_t)n);
-            if (!coup) { bad = 1; continue; }
+            double* xs = Jsplit ? (double*)malloc(sizeof(double) * 4 * (size_t)n) : NULL;
+            if (!coup || (Jsplit && !xs)) { free(coup); free(xs); bad = 1; continue; }
             for (int32_t s = 0; s < steps; ++s) {
-                coupling_rows(0, n, n, row_ptr, col, Jv, Jdense, th, coup);
+                if (Jsplit) {
+                    split_x_rows(0, n, n, th, xs);
+                    coupling_rows_bf16x3(0, n, n, Jsplit, xs, th, coup);
+                } else {
+                    coupling_rows(0, n, n, row_ptr, col, Jv, Jdense, th, coup);
+                }
                 update_rows(0, n, q, dt, K[s], Ks[s], sigma[s], seeds[r], (uint32_t)(step0 + s),
                             inst_of, local, coup, th);
             }
             free(coup);
+            free(xs);
         }
     } else {
         /* fewer replicas than threads: the oscillators of one replica are
@@ -184,7 +269,8 @@ static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, con
          * between the two loops of every step; every oscillator's arithmetic
          * is the same as in the serial loops */
         double* coup = (double*)malloc(sizeof(double) * (size_t)n);
-        if (!coup) bad = 1;
+        double* xs = Jsplit ? (double*)malloc(sizeof(double) * 4 * (size_t)n) : NULL;
+        if (!coup || (Jsplit && !xs)) bad = 1;
         for (int32_t r = 0; r < R && !bad; ++r) {
             double* th = theta + (int64_t)r * n;
 #pragma omp parallel num_threads(threads)
@@ -197,7 +283,13 @@ static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, con
                 const int32_t i0 = (int32_t)((int64_t)n * me / nt);
                 const int32_t i1 = (int32_t)((int64_t)n * (me + 1) / nt);
                 for (int32_t s = 0; s < steps; ++s) {
-                    coupling_rows(i0, i1, n, row_ptr, col, Jv, Jdense, th, coup);
+                    if (Jsplit) {
+                        split_x_rows(i0, i1, n, th, xs);
+#pragma omp barrier
+                        coupling_rows_bf16x3(i0, i1, n, Jsplit, xs, th, coup);
+                    } else {
+                        coupling_rows(i0, i1, n, row_ptr, col, Jv, Jdense, th, coup);
+                    }
 #pragma omp barrier
                     update_rows(i0, i1, q, dt, K[s], Ks[s], sigma[s], seeds[r],
                                 (uint32_t)(step0 + s), inst_of, local, coup, th);
@@ -206,6 +298,7 @@ static int run_common(int32_t n, const int64_t* row_ptr, const int32_t* col, con
             }
         }
         free(coup);
+        free(xs);
     }
     free(inst_of);
     free(local);
@@ -216,7 +309,7 @@ int orc_run_csr(int32_t n, const int64_t* row_ptr, const int32_t* col, const dou
                 int32_t q, int32_t R, int32_t steps, int64_t step0, double dt, const double* K,
                 const double* Ks, const double* sigma, const uint64_t* seeds, double* theta,
                 int32_t nthreads) {
-    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+    return run_common(n, row_ptr, col, J, NULL, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
                       theta, nthreads, 1, NULL, 0u);
 }
 
@@ -227,7 +320,7 @@ int orc_run_csr_instance(int32_t n, const int64_t* row_ptr, const int32_t* col, 
                          uint32_t b, int32_t q, int32_t R, int32_t steps, int64_t step0,
                          double dt, const double* K, const double* Ks, const double* sigma,
                          const uint64_t* seeds, double* theta, int32_t nthreads) {
-    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+    return run_common(n, row_ptr, col, J, NULL, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
                       theta, nthreads, 1, NULL, b);
 }
 
@@ -239,15 +332,36 @@ int orc_run_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col, co
                        int32_t steps, int64_t step0, double dt, const double* K, const double* Ks,
                        const double* sigma, const uint64_t* seeds, double* theta,
                        int32_t nthreads) {
-    return run_common(n, row_ptr, col, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
+    return run_common(n, row_ptr, col, J, NULL, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds,
                       theta, nthreads, n_inst, inst_off, 0u);
 }
 
 int orc_run_dense(int32_t n, const double* J, int32_t q, int32_t R, int32_t steps, int64_t step0,
                   double dt, const double* K, const double* Ks, const double* sigma,
                   const uint64_t* seeds, double* theta, int32_t nthreads) {
-    return run_common(n, NULL, NULL, NULL, J, q, R, steps, step0, dt, K, Ks, sigma, seeds, theta,
+    return run_common(n, NULL, NULL, NULL, J, NULL, q, R, steps, step0, dt, K, Ks, sigma, seeds, theta,
                       nthreads, 1, NULL, 0u);
+}
+
+/* Dense coupling with BF16x3 split products (see coupling_rows_bf16x3); the
+ * rest of the step is the FP64 step of Algorithm 1. */
+int orc_run_dense_bf16x3(int32_t n, const double* J, int32_t q, int32_t R, int32_t steps,
+                         int64_t step0, double dt, const double* K, const double* Ks,
+                         const double* sigma, const uint64_t* seeds, double* theta,
+                         int32_t nthreads) {
+    if (n < 1) return -1;
+    double* Jsp = (double*)malloc(sizeof(double) * 2 * (size_t)n * n);
+    if (!Jsp) return -1;
+    for (int32_t i = 0; i < n; ++i)
+        for (int32_t j = 0; j < n; ++j) {
+            const int64_t k = (int64_t)i * n + j;
+            if (i == j) { Jsp[k] = 0.0; Jsp[(size_t)n * n + k] = 0.0; }
+            else split3((float)J[k], &Jsp[k], &Jsp[(size_t)n * n + k]);
+        }
+    const int rc = run_common(n, NULL, NULL, NULL, NULL, Jsp, q, R, steps, step0, dt, K, Ks,
+                              sigma, seeds, theta, nthreads, 1, NULL, 0u);
+    free(Jsp);
+    return rc;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -438,11 +552,11 @@ int orc_adjoint_csr_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col
     for (int32_t r = 0; r < R; ++r) {
         /* forward, keeping every state */
         memcpy(traj, theta0 + (size_t)r * N, sizeof(double) * N);
-        if (run_common(n, row_ptr, col, J, NULL, q, 1, 0, step0, dt, K, Ks, sigma, seeds + r,
+        if (run_common(n, row_ptr, col, J, NULL, NULL, q, 1, 0, step0, dt, K, Ks, sigma, seeds + r,
                        traj, 1, n_inst, inst_off, 0u) != 0) { total = NAN; break; }
         for (int32_t s = 0; s < steps; ++s) {
             memcpy(traj + N * (s + 1), traj + N * s, sizeof(double) * N);
-            if (run_common(n, row_ptr, col, J, NULL, q, 1, 1, step0 + s, dt, K + s, Ks + s,
+            if (run_common(n, row_ptr, col, J, NULL, NULL, q, 1, 1, step0 + s, dt, K + s, Ks + s,
                            sigma + s, seeds + r, traj + N * (s + 1), 1, n_inst, inst_off, 0u) != 0) {
                 total = NAN;
                 break;
