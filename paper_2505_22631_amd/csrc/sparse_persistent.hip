@@ -114,8 +114,10 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     unsigned char* col8 = smem + (size_t)8 * 4 * plane;            // [4 * plane] (readout)
     double* red = reinterpret_cast<double*>(col8 + ((4 * plane + 15) & ~15));  // [W]
     double* tstack = red + W;                                                   // tree levels
+    // readout state of thread 0: [0] improved flag, [1] best step, [2..3] best H
     int* flag = reinterpret_cast<int*>(tstack + kSliceTreeLevels);
-    double* part = reinterpret_cast<double*>(flag + 4);             // [WS][G][64], RPL < 4
+    double* best_lds = reinterpret_cast<double*>(flag + 2);
+    double* part = reinterpret_cast<double*>(flag + 8);             // [WS][G][64], RPL < 4
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -153,11 +155,13 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             if (slice < S) sc[j * plane + m] = make_float2(sin_turn(u), cos_turn(u));
         }
     }
+    if (threadIdx.x == 0) {
+        *best_lds = DBL_MAX;
+        flag[1] = -1;
+    }
     __syncthreads();
 
     const float sqrt_dt = __builtin_sqrtf(a.dt);
-    double best = DBL_MAX;
-    int32_t best_at = -1;
 
     // Schedules arrive 64 steps at a time, one step per lane, with the next
     // chunk's vector loads in flight while the current chunk is used; each
@@ -326,15 +330,20 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             // 1, 2, ..., 32), which is the pairwise tree over the slice's 256
             // rows; thread 0 folds the slices, in order, into the tree over
             // slices, one round of WS slices at a time.
+            // The loops below are kept rolled (the slice's descriptor is
+            // re-read) so the readout, which runs only every M steps, adds no
+            // registers to the step loop.
             TreeAccN<kSliceTreeLevels> tree(tstack);
-#pragma unroll
+#pragma unroll 1
             for (int k = 0; k < MS; ++k) {
                 if (k * WS >= S) break;  // uniform over the workgroup
                 const int slice = ws + k * WS;
                 double v = 0.0;
                 if (slice < S) {
+                    const int2 d = a.desc[slice0 + slice];
+                    const int sb = __builtin_amdgcn_readfirstlane(d.x);
+                    const int D2 = __builtin_amdgcn_readfirstlane(d.y) >> 1;
                     const int m = slice * 64 + lane;
-                    const int D2 = sdeg[k] >> 1;
                     double rs[RPL];
 #pragma unroll
                     for (int jj = 0; jj < RPL; ++jj) {
@@ -343,7 +352,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                         const int own = 4 * m + j;
                         double row = 0.0;
                         for (int e2 = 0; e2 < D2; ++e2) {
-                            const int4 e = load_pair(rsrc, voff, (sbase[k] + j * D2 + e2) * 1024);
+                            const int4 e = load_pair(rsrc, voff, (sb + j * D2 + e2) * 1024);
                             const int c0 = col8[e.x >> 3], c1 = col8[e.z >> 3];
                             const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.w);
                             // upper triangle only: the neighbour's index from its slot
@@ -384,17 +393,17 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 const int kread = (s + a.M) / a.M - 1;
                 if (a.trace) a.trace[(int64_t)kread * a.R * a.I + out_id] = H;
                 int improved = 0;
-                if (H < best) {
-                    best = H;
-                    best_at = (int32_t)(a.step0 + s + 1);
+                if (H < *best_lds) {
+                    *best_lds = H;
+                    flag[1] = (int32_t)(a.step0 + s + 1);
                     improved = 1;
                 }
-                *flag = improved;
+                flag[0] = improved;
             }
             __syncthreads();
-            if (*flag && a.best_colour) {
+            if (flag[0] && a.best_colour) {
                 int8_t* bc = a.best_colour + (int64_t)r * a.n_total + off;
-#pragma unroll
+#pragma unroll 1
                 for (int k = 0; k < MS; ++k) {
                     const int slice = ws + k * WS;
                     const int m = slice * 64 + lane;
@@ -424,7 +433,8 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
         }
     }
     if (threadIdx.x == 0) {
-        if (a.best_h) a.best_h[out_id] = best_at >= 0 ? best : __builtin_inf();
+        const int32_t best_at = flag[1];
+        if (a.best_h) a.best_h[out_id] = best_at >= 0 ? *best_lds : __builtin_inf();
         if (a.best_step) a.best_step[out_id] = best_at;
     }
 }
@@ -473,7 +483,7 @@ constexpr size_t kLdsLimit = 160 * 1024;
 size_t lds_bytes(int plane, int tb, int rpl) {
     size_t b = (size_t)8 * 4 * plane;                 // (sin, cos) table
     b += ((size_t)4 * plane + 15) & ~(size_t)15;      // colours for readout
-    b += sizeof(double) * (tb / 64 + kSliceTreeLevels) + 16;  // reduction, tree levels, flag
+    b += sizeof(double) * (tb / 64 + kSliceTreeLevels) + 32;  // reduction, tree levels, readout state
     if (rpl < 4) b += sizeof(double) * (size_t)tb;    // quads' partial row sums (readout)
     return b;
 }
