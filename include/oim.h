@@ -45,6 +45,7 @@
 #ifndef OIM_H
 #define OIM_H
 
+#include <stddef.h>
 #include <stdint.h>
 #include <hip/hip_runtime_api.h>
 
@@ -191,6 +192,29 @@ typedef struct {
 int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
             const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
             uint32_t* phase, const oim_readout* readout, hipStream_t stream);
+
+/* oim_run for callers that cannot allocate device memory: code under
+ * hipGraph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments, checks, results (bit for bit) and asynchrony as oim_run,
+ * but no allocation of any kind: the LDS-resident loop needs no workspace;
+ * the stepwise and dense loops take theirs from a fixed device array of
+ * oim_noalloc_scratch_bytes() (64 MiB) inside the library, one per device,
+ * held until the process ends, and launch their per-step kernels directly
+ * (no hipGraph is instantiated).  A run whose workspace exceeds the array is
+ * rejected with OIM_E_UNSUPPORTED (the stepwise loop needs about
+ * 20 * n * ceil(R / 64) * 64 bytes, the dense loop
+ * 20 * ceil(n / 128) * 128 * ceil(R / 64) * 64 bytes); so is an FP32 run on
+ * a dense problem whose FP32 image of J has not been made by an earlier
+ * oim_run with OIM_PREC_FP32.  Every call on one device shares that device's
+ * array: calls that overlap on one device (other streams or threads) race
+ * and must not be issued.  Errors: as oim_run, without OIM_E_NOMEM. */
+int oim_run_noalloc(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* Ks,
+                    const float* sigma, const uint64_t* seeds, int64_t step0, float* theta,
+                    uint32_t* phase, const oim_readout* readout, hipStream_t stream);
+
+/* Size in bytes of the per-device array oim_run_noalloc takes its
+ * workspace from. */
+size_t oim_noalloc_scratch_bytes(void);
 
 /* ------------------------------------------------------------------------
  * Launch-shape autotuning of the LDS-resident loop (the per-thread batch of

@@ -26,6 +26,7 @@ __all__ = [
     "OIM_LOOP_AUTO", "OIM_LOOP_PERSISTENT", "OIM_LOOP_STEPWISE", "OIM_PREC_FP32",
     "OIM_PREC_BF16X3", "OIM_SCHED_PER_REPLICA", "OimError", "Problem", "oim_abi_version", "oim_problem_from_csr",
     "oim_problem_from_csr_blocks", "oim_problem_from_dense", "oim_problem_destroy", "oim_problem_info_get", "oim_run",
+    "oim_run_noalloc", "oim_noalloc_scratch_bytes",
     "oim_round", "oim_cut", "oim_conflicts", "oim_energy", "oim_phase_from_theta",
     "oim_theta_from_phase", "oim_autotune", "oim_set_tuning",
     "oim_adjoint_checkpoint_words", "oim_adjoint_forward",
@@ -124,12 +125,8 @@ def n_readouts(steps: int, readout_every: int) -> int:
     return 0 if readout_every <= 0 else -(-int(steps) // int(readout_every))
 
 
-def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0, step0=0,
-            phase=None, trace=None, best_h=None, best_step=None, best_colour=None,
-            stream=None):
-    """Run len(K) Euler-Maruyama steps on theta[R][n] (FP32, radians, in place).
-    With `phase` (uint32 [R][n] phase words) the run starts from and updates
-    the exact device state."""
+def _run_args(h, n, theta, K, Ks, sigma, seeds, q, dt, readout_every, flags, step0, phase,
+              trace, best_h, best_step, best_colour, stream):
     if theta.dim() != 2 or theta.shape[1] != n:
         raise ValueError("theta must be [R][n]")
     R = int(theta.shape[0])
@@ -145,13 +142,37 @@ def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0
                  _dev(best_h, torch.float64, (RI,), "best_h", True),
                  _dev(best_step, torch.int32, (RI,), "best_step", True),
                  _dev(best_colour, torch.int8, (R, n), "best_colour", True))
-    check(lib().oim_run(h, ctypes.byref(cfg), _dev(K, torch.float32, sshape, "K"),
-                        _dev(Ks, torch.float32, sshape, "Ks"),
-                        _dev(sigma, torch.float32, sshape, "sigma"),
-                        _dev(seeds, torch.uint64, (R,), "seeds"), int(step0),
-                        _dev(theta, torch.float32, None, "theta"),
-                        _dev(phase, torch.uint32, (R, n), "phase", True), ctypes.byref(ro),
-                        _stream(stream)))
+    return (h, ctypes.byref(cfg), _dev(K, torch.float32, sshape, "K"),
+            _dev(Ks, torch.float32, sshape, "Ks"), _dev(sigma, torch.float32, sshape, "sigma"),
+            _dev(seeds, torch.uint64, (R,), "seeds"), int(step0),
+            _dev(theta, torch.float32, None, "theta"),
+            _dev(phase, torch.uint32, (R, n), "phase", True), ctypes.byref(ro),
+            _stream(stream)), (cfg, ro)
+
+
+def oim_run(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0, step0=0,
+            phase=None, trace=None, best_h=None, best_step=None, best_colour=None,
+            stream=None):
+    """Run len(K) Euler-Maruyama steps on theta[R][n] (FP32, radians, in place).
+    With `phase` (uint32 [R][n] phase words) the run starts from and updates
+    the exact device state."""
+    args, keep = _run_args(h, n, theta, K, Ks, sigma, seeds, q, dt, readout_every, flags, step0,
+                           phase, trace, best_h, best_step, best_colour, stream)
+    check(lib().oim_run(*args))
+
+
+def oim_run_noalloc(h, n, theta, K, Ks, sigma, seeds, *, q, dt, readout_every=0, flags=0,
+                    step0=0, phase=None, trace=None, best_h=None, best_step=None,
+                    best_colour=None, stream=None):
+    """oim_run without any device allocation (workspace from the library's
+    fixed per-device array; see oim_noalloc_scratch_bytes)."""
+    args, keep = _run_args(h, n, theta, K, Ks, sigma, seeds, q, dt, readout_every, flags, step0,
+                           phase, trace, best_h, best_step, best_colour, stream)
+    check(lib().oim_run_noalloc(*args))
+
+
+def oim_noalloc_scratch_bytes() -> int:
+    return int(lib().oim_noalloc_scratch_bytes())
 
 
 def oim_autotune(h, n, theta, K, Ks, sigma, seeds, *, q, dt, trial_steps, stream=None) -> dict:

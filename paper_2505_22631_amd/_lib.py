@@ -62,6 +62,9 @@ PROTOTYPES = {
     "oim_problem_info_get": (ctypes.c_int, [_P, ctypes.POINTER(ProblemInfo)]),
     "oim_run": (ctypes.c_int, [_P, ctypes.POINTER(RunCfg), _P, _P, _P, _P, _i64, _P, _P,
                                ctypes.POINTER(Readout), _P]),
+    "oim_run_noalloc": (ctypes.c_int, [_P, ctypes.POINTER(RunCfg), _P, _P, _P, _P, _i64, _P,
+                                       _P, ctypes.POINTER(Readout), _P]),
+    "oim_noalloc_scratch_bytes": (ctypes.c_size_t, []),
     "oim_phase_from_theta": (ctypes.c_int, [_i64, _P, _P, _P]),
     "oim_theta_from_phase": (ctypes.c_int, [_i64, _P, _P, _P]),
     "oim_round": (ctypes.c_int, [_i32, _i64, _P, _P, _P]),

@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liboim.so")
 OBJ = os.path.join(HERE, "_build")
 SOURCES = ["api.cpp", "validate.cpp", "readout.hip", "sparse_persistent.hip", "stepwise.hip",
-           "dense.hip", "adjoint.hip"]
+           "dense.hip", "adjoint.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 VALU forms are disabled for every device compile.
