@@ -345,25 +345,43 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                     const int D2 = __builtin_amdgcn_readfirstlane(d.y) >> 1;
                     const int m = slice * 64 + lane;
                     double rs[RPL];
+                    int ci[RPL];
 #pragma unroll
                     for (int jj = 0; jj < RPL; ++jj) {
-                        const int j = j0 + jj;
-                        const int ci = col8[j * plane + m];
-                        const int own = 4 * m + j;
-                        double row = 0.0;
-                        for (int e2 = 0; e2 < D2; ++e2) {
-                            const int4 e = load_pair(rsrc, voff, (sb + j * D2 + e2) * 1024);
-                            const int c0 = col8[e.x >> 3], c1 = col8[e.z >> 3];
-                            const float w0 = __int_as_float(e.y), w1 = __int_as_float(e.w);
-                            // upper triangle only: the neighbour's index from its slot
-                            const bool up0 = slot_index(e.x >> 3, plane) > own;
-                            const bool up1 = slot_index(e.z >> 3, plane) > own;
-                            const float t0 = (q == 2) ? (ci == c0 ? w0 : -w0) : (ci == c0 ? w0 : 0.f);
-                            const float t1 = (q == 2) ? (ci == c1 ? w1 : -w1) : (ci == c1 ? w1 : 0.f);
-                            row += up0 ? (double)t0 : 0.0;
-                            row += up1 ? (double)t1 : 0.0;
+                        rs[jj] = 0.0;
+                        ci[jj] = col8[(j0 + jj) * plane + m];
+                    }
+                    // UR entry pairs of every row per iteration (8 loads in
+                    // all for whole quads, 4 for split rows, which have fewer
+                    // registers to spare), issued before the first is used;
+                    // each row still adds its terms in entry order
+                    constexpr int UR = RPL == 4 ? 2 : 4 / RPL;
+                    for (int e2 = 0; e2 < D2; e2 += UR) {
+                        int4 e[RPL][UR];
+#pragma unroll
+                        for (int jj = 0; jj < RPL; ++jj)
+#pragma unroll
+                            for (int h = 0; h < UR; ++h)
+                                if (h < 2 || e2 + h < D2)
+                                    e[jj][h] = load_pair(rsrc, voff + h * 1024, (sb + (j0 + jj) * D2 + e2) * 1024);
+#pragma unroll
+                        for (int jj = 0; jj < RPL; ++jj) {
+                            const int own = 4 * m + j0 + jj;
+#pragma unroll
+                            for (int h = 0; h < UR; ++h) {
+                                if (h >= 2 && e2 + h >= D2) break;
+                                const int4 x = e[jj][h];
+                                const int c0 = col8[x.x >> 3], c1 = col8[x.z >> 3];
+                                const float w0 = __int_as_float(x.y), w1 = __int_as_float(x.w);
+                                // upper triangle only: the neighbour's index from its slot
+                                const bool up0 = slot_index(x.x >> 3, plane) > own;
+                                const bool up1 = slot_index(x.z >> 3, plane) > own;
+                                const float t0 = (q == 2) ? (ci[jj] == c0 ? w0 : -w0) : (ci[jj] == c0 ? w0 : 0.f);
+                                const float t1 = (q == 2) ? (ci[jj] == c1 ? w1 : -w1) : (ci[jj] == c1 ? w1 : 0.f);
+                                rs[jj] += up0 ? (double)t0 : 0.0;
+                                rs[jj] += up1 ? (double)t1 : 0.0;
+                            }
                         }
-                        rs[jj] = row;
                     }
                     if constexpr (RPL == 4) v = (rs[0] + rs[1]) + (rs[2] + rs[3]);
                     else if constexpr (RPL == 2) v = rs[0] + rs[1];

@@ -63,7 +63,23 @@ struct StepArgs {
     const CallArgs* call;
     int k;                // position of this node in the chunk
     int n, R, Rp, q;
+    int gx;               // quad blocks (workgroups per replica block)
 };
+
+// Workgroup id -> (quad block, replica block).  Consecutive workgroup ids go
+// to the 8 XCDs in turn; each XCD is given a contiguous range of quad
+// blocks (all of one replica block before the next), so the neighbour rows
+// a workgroup gathers (the quads around its own) were mostly fetched into
+// the same XCD's L2 by its neighbours.  A bijection on [0, nb): the blocks
+// past the last multiple of 8 keep their index.
+__device__ __forceinline__ void step_block(int b, int nb, int gx, int& qb, int& rb) {
+    constexpr int kXcds = 8;
+    const int full = nb / kXcds * kXcds;
+    int t = b;
+    if (b < full) t = (b % kXcds) * (full / kXcds) + b / kXcds;
+    rb = t / gx;
+    qb = t - rb * gx;
+}
 
 template <int QM>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
@@ -71,9 +87,11 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int s = c.base + a.k;
     if (s >= c.steps) return;
     const int lane = threadIdx.x & 63;
-    const int m = blockIdx.x * kQuadsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int qb, rb;
+    step_block(blockIdx.x, gridDim.x, a.gx, qb, rb);
+    const int m = qb * kQuadsPerBlock + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     if (4 * m >= a.n) return;
-    const int r = blockIdx.y * 64 + lane;
+    const int r = rb * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
     const uint32_t t = (uint32_t)(c.step0 + s);
     const float dt = c.dt;
@@ -238,18 +256,50 @@ struct BestArgs {
 };
 
 // One workgroup per replica: H = -(the pairwise tree over the blocks'
-// partials), trace entry, best-so-far and the colours of a new best.
+// partials), trace entry, best-so-far and the colours of a new best.  The
+// partials, zero-padded to a power of two P, are taken in rounds of
+// CH = min(P, 4096) values; in a round each of the 256 threads folds an
+// aligned chunk of CH / 256 (at most 16) values by the pairwise tree in
+// registers, the 256 chunk sums are folded pairwise in LDS, and thread 0
+// pushes the round's sum into a tree over rounds.  This is the pairwise tree
+// over the padded sequence (padding zeros add exactly).
 __global__ __launch_bounds__(256) void stepwise_best_kernel(BestArgs a) {
     __shared__ int improved;
+    __shared__ double sums[256];
     __shared__ double stack[TreeAcc::kLevels];
     const CallArgs& c = *a.call;
     const int s = a.k < 0 ? c.steps - 1 : c.base + a.k;
     if (s >= c.steps) return;
     const int r = blockIdx.x;
+    int64_t P = 1;
+    while (P < a.nblocks) P <<= 1;
+    const int CH = P < 4096 ? (int)P : 4096;
+    const int B = CH >= 256 ? CH / 256 : 1;
+    const int64_t rounds = P / CH;
+    TreeAcc outer(stack);
+    for (int64_t rd = 0; rd < rounds; ++rd) {
+        const int64_t first = rd * CH + (int64_t)threadIdx.x * B;
+        double v[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            v[i] = (i < B && first + i < a.nblocks) ? a.part[(size_t)(first + i) * a.Rp + r] : 0.0;
+        // the tree over 16 slots; slots past B hold +0, so the result is the
+        // tree over the chunk's B values
+#pragma unroll
+        for (int len = 16; len > 1; len >>= 1)
+#pragma unroll
+            for (int i = 0; i < len / 2; ++i) v[i] = v[2 * i] + v[2 * i + 1];
+        sums[threadIdx.x] = v[0];
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            if ((threadIdx.x & (2 * d - 1)) == 0) sums[threadIdx.x] = sums[threadIdx.x] + sums[threadIdx.x + d];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) outer.push(sums[0]);
+        __syncthreads();
+    }
     if (threadIdx.x == 0) {
-        TreeAcc tree(stack);
-        for (int b = 0; b < a.nblocks; ++b) tree.push(a.part[(size_t)b * a.Rp + r]);
-        const double H = -tree.finish();
+        const double H = -outer.finish();
         const int kread = (s + a.M) / a.M - 1;
         if (c.trace) c.trace[(size_t)kread * a.R + r] = H;
         improved = (kread == 0 || H < a.best[r]) ? 1 : 0;
@@ -402,6 +452,7 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     sa.R = R;
     sa.Rp = Rp;
     sa.q = cfg->q;
+    sa.gx = gx;
     ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, call, 0, n, Rp, cfg->q};
     BestArgs ba{};
     ba.part = part;
@@ -425,7 +476,7 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
             sa.tin = odd ? T1 : T0;
             sa.tout = odd ? T0 : T1;
             sa.k = k;
-            hipLaunchKernelGGL(fn, dim3(gx, Rp / 64), dim3(256), 0, s, sa);
+            hipLaunchKernelGGL(fn, dim3(gx * (Rp / 64)), dim3(256), 0, s, sa);
             int rc = check_launch("stepwise_step_kernel");
             if (rc) return rc;
             if (M > 0 && (k + 1) % M == 0) {

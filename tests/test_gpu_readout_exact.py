@@ -120,6 +120,33 @@ def test_in_run_readout_real_weights_exact(oim, orc, loop):
     print(f"{loop}: best H {ro['best_h'].tolist()}", flush=True)
 
 
+def test_stepwise_readout_exact_many_blocks(oim, orc):
+    # 70000 oscillators: 4375 row blocks of partial sums, padded to 8192,
+    # folded in two rounds of 4096 with 16 per thread -- still the fixed
+    # order, so equal to the oracle's
+    n = 70000
+    rng = np.random.default_rng(9)
+    a, b = rng.integers(0, n, size=(2, 3 * n))
+    keep = a != b
+    pairs = np.unique(np.stack([np.minimum(a, b)[keep], np.maximum(a, b)[keep]], axis=1), axis=0)
+    w = (rng.standard_normal(len(pairs)) * np.exp(rng.uniform(-6, 3, len(pairs))))
+    g = synth.csr_from_edges(n, pairs[:, 0], pairs[:, 1], w.astype(np.float32))
+    J = (-g.w).astype(np.float32)
+    R, q, steps, M = 2, 2, 20, 10
+    with oim.Problem.from_csr(g.n, g.row_ptr, g.col, J) as prob:
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, steps)
+        th0 = synth.theta0(R, g.n, seed=3)
+        ph = _t(_words(th0))
+        out = oim.run(prob, _t(th0), _t(K), _t(Ks), _t(sg), _t(synth.seeds(R, 4)), q=q, dt=DT,
+                      readout_every=M, flags=oim.OIM_LOOP_STEPWISE, want_best=True, phase=ph)
+        ro = {k: v.cpu().numpy() for k, v in out.items()}
+        w = ph.cpu().numpy()
+    for r in range(R):
+        assert ro["best_h"][r] == orc.h_model_fixed(g.row_ptr, g.col, J, q, ro["best_colour"][r])
+        last = orc.h_model_fixed(g.row_ptr, g.col, J, q, _colours_from_words(w[r], q))
+        assert ro["trace"][-1, r] == last
+
+
 def test_batch_in_run_readout_real_weights_exact(oim, orc):
     gs = [_real_graph(n=n, deg=5.0, seed=30 + k) for k, n in enumerate([700, 260, 1031, 64])]
     big, off = synth.block_diagonal(gs)
