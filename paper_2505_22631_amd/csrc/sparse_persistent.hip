@@ -64,6 +64,7 @@ struct PersistArgs {
     int8_t* best_colour;  // [R][n_total]
     int32_t R;
     int32_t sched_stride;  // 0: one schedule for all replicas; steps: [R][steps]
+    int32_t slice_sums;    // 1: the readout keeps every slice's sum in LDS (room for it)
 };
 
 // Tree levels of the in-run readout's sum over slices (2^8 slices at most).
@@ -118,6 +119,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     int* flag = reinterpret_cast<int*>(tstack + kSliceTreeLevels);
     double* best_lds = reinterpret_cast<double*>(flag + 2);
     double* part = reinterpret_cast<double*>(flag + 8);             // [WS][G][64], RPL < 4
+    double* ssum = part + (RPL < 4 ? TB : 0);                        // [MS * WS], slice_sums
 
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -328,8 +330,11 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             // its padding adds zeros); a quad's rows fold as (r0 + r1) +
             // (r2 + r3) and the lanes by the xor butterfly (partner distance
             // 1, 2, ..., 32), which is the pairwise tree over the slice's 256
-            // rows; thread 0 folds the slices, in order, into the tree over
-            // slices, one round of WS slices at a time.
+            // rows.  The tree over slices: with room in LDS every slice's sum
+            // is stored and wave 0 folds them (two per lane, then the lanes by
+            // distance 1, 2, ..., 32, lower index first); otherwise thread 0
+            // folds them, in order, into the same tree, one round of WS
+            // slices at a time.
             // The loops below are kept rolled (the slice's descriptor is
             // re-read) so the readout, which runs only every M steps, adds no
             // registers to the step loop.
@@ -399,15 +404,37 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                 }
                 if (g == 0 && slice < S) {
                     for (int o = 1; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-                    if (lane == 0) red[ws] = v;
+                    if (lane == 0) {
+                        if (a.slice_sums) ssum[slice] = v;
+                        else red[ws] = v;
+                    }
+                }
+                if (a.slice_sums) {
+                    // part is reused by the next slice
+                    if constexpr (RPL < 4) __syncthreads();
+                    continue;
                 }
                 __syncthreads();
                 if (threadIdx.x == 0)
                     for (int w = 0; w < WS && k * WS + w < S; ++w) tree.push(red[w]);
                 __syncthreads();
             }
+            double total = 0.0;
+            if (a.slice_sums) {
+                __syncthreads();
+                if (wave == 0) {
+                    // S <= 128 slices: two per lane, zero-padded
+                    const double v0 = 2 * lane < S ? ssum[2 * lane] : 0.0;
+                    const double v1 = 2 * lane + 1 < S ? ssum[2 * lane + 1] : 0.0;
+                    double v = v0 + v1;
+                    for (int o = 1; o < 64; o <<= 1) v = v + __shfl_down(v, o, 64);
+                    total = v;
+                }
+            } else if (threadIdx.x == 0) {
+                total = tree.finish();
+            }
             if (threadIdx.x == 0) {
-                const double H = -tree.finish();
+                const double H = -total;
                 const int kread = (s + a.M) / a.M - 1;
                 if (a.trace) a.trace[(int64_t)kread * a.R * a.I + out_id] = H;
                 int improved = 0;
@@ -498,11 +525,14 @@ const Variant kVariants[] = {
 
 constexpr size_t kLdsLimit = 160 * 1024;
 
-size_t lds_bytes(int plane, int tb, int rpl) {
+// LDS of a launch; with slice_sums, room for the readout's per-slice sums
+// (slices covered by the variant) too.
+size_t lds_bytes(int plane, int tb, int rpl, int covered = 0) {
     size_t b = (size_t)8 * 4 * plane;                 // (sin, cos) table
     b += ((size_t)4 * plane + 15) & ~(size_t)15;      // colours for readout
     b += sizeof(double) * (tb / 64 + kSliceTreeLevels) + 32;  // reduction, tree levels, readout state
     if (rpl < 4) b += sizeof(double) * (size_t)tb;    // quads' partial row sums (readout)
+    b += sizeof(double) * (size_t)covered;            // per-slice sums (readout), if used
     return b;
 }
 
@@ -611,7 +641,10 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
     a.sched_stride = sched_stride;
     const int qi = cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0;
     KernelFn fn = v->fn[qi];
-    const size_t lds = lds_bytes(plane, v->tb, v->rpl);
+    // the readout keeps per-slice sums in LDS when there is room for them
+    const size_t lds_fast = lds_bytes(plane, v->tb, v->rpl, v->covers());
+    a.slice_sums = (a.M > 0 && lds_fast <= kLdsLimit) ? 1 : 0;
+    const size_t lds = a.slice_sums ? lds_fast : lds_bytes(plane, v->tb, v->rpl);
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return hip_error(e, "hipFuncSetAttribute");

@@ -147,6 +147,32 @@ def test_stepwise_readout_exact_many_blocks(oim, orc):
         assert ro["trace"][-1, r] == last
 
 
+@pytest.mark.parametrize("rows,cols", [(100, 100), (120, 150)])
+def test_lds_resident_readout_tree_over_slices(oim, orc, rows, cols):
+    # the 100 x 100 torus (40 slices) keeps every slice's sum in LDS; the
+    # 120 x 150 torus (71 slices) leaves no room for them and folds them one
+    # round at a time: both give the fixed-order value
+    g0 = synth.torus(rows, cols, seed=4)
+    rng = np.random.default_rng(rows)
+    ei, ej, _ = g0.upper_edges()
+    w = (rng.standard_normal(ei.size) * np.exp(rng.uniform(-4, 2, ei.size))).astype(np.float32)
+    g = synth.csr_from_edges(g0.n, ei, ej, w)
+    J = (-g.w).astype(np.float32)
+    R, q, steps, M = 2, 2, 30, 10
+    with oim.Problem.from_csr(g.n, g.row_ptr, g.col, J) as prob:
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, steps)
+        th0 = synth.theta0(R, g.n, seed=rows + cols)
+        ph = _t(_words(th0))
+        out = oim.run(prob, _t(th0), _t(K), _t(Ks), _t(sg), _t(synth.seeds(R, 1)), q=q, dt=DT,
+                      readout_every=M, flags=oim.OIM_LOOP_PERSISTENT, want_best=True, phase=ph)
+        ro = {k: v.cpu().numpy() for k, v in out.items()}
+        w = ph.cpu().numpy()
+    for r in range(R):
+        assert ro["best_h"][r] == orc.h_model_fixed(g.row_ptr, g.col, J, q, ro["best_colour"][r])
+        last = orc.h_model_fixed(g.row_ptr, g.col, J, q, _colours_from_words(w[r], q))
+        assert ro["trace"][-1, r] == last
+
+
 def test_batch_in_run_readout_real_weights_exact(oim, orc):
     gs = [_real_graph(n=n, deg=5.0, seed=30 + k) for k, n in enumerate([700, 260, 1031, 64])]
     big, off = synth.block_diagonal(gs)
