@@ -346,9 +346,13 @@ int oim_adjoint_forward(oim_problem p, const oim_adjoint_cfg* cfg, const float* 
  * arguments: recomputes every C-step segment from its checkpoint, runs the
  * adjoint recurrence back through it, and writes dL/dK, dL/dKs, dL/dsigma as
  * device FP64 [steps] (sums over replicas and instances in a fixed order).
- * Uses a workspace cached in p (C * R * slots words plus 128 bytes per step
- * and workgroup); one stream at a time per problem.  Errors as the forward
- * pass, plus OIM_E_NOMEM. */
+ * The recomputation of a segment runs on a second stream owned by p, made on
+ * the first backward call (default priority), overlapping the adjoint of the
+ * later segment on `stream`; the work forks from and joins back into
+ * `stream`, so the call stays asynchronous and later work on `stream` sees
+ * the gradients.  Uses a workspace cached in p (2 (C + 1) R slots words,
+ * R slots floats, plus 128 bytes per step and workgroup); one stream at a
+ * time per problem.  Errors as the forward pass, plus OIM_E_NOMEM. */
 int oim_adjoint_backward(oim_problem p, const oim_adjoint_cfg* cfg, const float* K,
                          const float* Ks, const float* sigma, const uint64_t* seeds,
                          int64_t step0, const uint32_t* ckpt, double* gK, double* gKs,

@@ -71,8 +71,10 @@ struct AdjArgs {
     uint32_t* ckpt;        // [nseg][R][P] phase words
     float* thetaT;         // [R][n_total] or null
     double* loss;          // [R * I] or null
-    uint32_t* seg;         // [C][R][P] scratch (backward)
+    uint32_t* seg;         // [C + 1][R][P] states of one segment (backward)
     float4* gpart;         // [steps][R * I][kAdjWaves] (backward)
+    float* lam;            // [R][P] adjoint state between segments (backward)
+    int cur_seg;           // segment of this launch (backward)
 };
 
 template <int QM>
@@ -521,8 +523,48 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
     }
 }
 
+// Backward pass, segment a.cur_seg (steps t0 .. t1 - 1), in two kernels that
+// run on two streams so that the recomputation of one segment overlaps the
+// adjoint of the next (later) one, each kernel on its own half of the CUs.
+//
+// Recompute: the segment's states from its checkpoint, written to a.seg
+// (slot s - t0 holds the state at step s; the last segment also computes its
+// final step and stores the state at t1 in slot t1 - t0).  The Philox noise is
+// a pure function of (seed, oscillator, step, instance) and every placement
+// of the rows gives the same bits, so these are the forward pass's states.
 template <int QM, int MODE>
-__global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
+__global__ __launch_bounds__(kAdjTB) void adjoint_recompute_kernel(AdjArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const Ctx x = make_ctx(a);
+    const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
+    float4* const tabs = reinterpret_cast<float4*>(smem);
+    auto tab = [&](int k) { return tabs + (size_t)k * (a.tabN + 1); };
+    const int sg = a.cur_seg;
+    const int t0 = sg * a.C;
+    const int t1 = t0 + a.C < a.steps ? t0 + a.C : a.steps;
+    const bool last = sg == a.nseg - 1;
+    uint32_t u[kAdjQPT][4];
+    load_words(a, x, a.ckpt, sg, u);
+    put_sc(x, tab(0), u);
+    __syncthreads();
+    int p = 0;
+    for (int s = t0; s < t1; ++s) {
+        store_words(a, x, a.seg, s - t0, u);
+        if (s + 1 < t1 || last) {
+            fwd_step<QM>(a, x, g, s, tab(p), tab(p ^ 1), u);
+            p ^= 1;
+            __syncthreads();
+        }
+    }
+    if (last) store_words(a, x, a.seg, t1 - t0, u);
+}
+
+// Adjoint: the recurrence back through the segment's stored states, from the
+// adjoint state left by the later segment in a.lam (or, for the last
+// segment, lam_T from the final phases); the adjoint state at t0 goes back
+// to a.lam.  Per-step gradient partials per wave go to a.gpart.
+template <int QM, int MODE>
+__global__ __launch_bounds__(kAdjTB) void adjoint_segment_kernel(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Ctx x = make_ctx(a);
     const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
@@ -532,90 +574,98 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_backward_kernel(AdjArgs a) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int nwg = a.R * a.I;
     const float sqrt_dt = __builtin_sqrtf(a.dt);
+    const int sg = a.cur_seg;
+    const int t0 = sg * a.C;
+    const int t1 = t0 + a.C < a.steps ? t0 + a.C : a.steps;
     uint32_t u[kAdjQPT][4];
     float lam[kAdjQPT][4];
     int p = 0;  // table written next
-    for (int sg = a.nseg - 1; sg >= 0; --sg) {
-        const int t0 = sg * a.C;
-        const int t1 = t0 + a.C < a.steps ? t0 + a.C : a.steps;
-        const bool last = sg == a.nseg - 1;
-        // recompute the segment's states from its checkpoint
-        load_words(a, x, a.ckpt, sg, u);
+    if (sg == a.nseg - 1) {
+        // lam_T from the final phases
+        load_words(a, x, a.seg, t1 - t0, u);
         put_sc(x, tab(p), u);
         __syncthreads();
-        for (int s = t0; s < t1; ++s) {
-            store_words(a, x, a.seg, s - t0, u);
-            if (s + 1 < t1 || last) {
-                fwd_step<QM>(a, x, g, s, tab(p), tab(p ^ 1), u);
-                p ^= 1;
-                __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int m = threadIdx.x + k * kAdjTB;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * m + j;
+                lam[k][j] = 0.f;
+                if (m >= x.nq || i >= x.nb) continue;
+                float A, B, Cl, Dl;
+                gather<false>(g, tab(p), i, A, B, Cl, Dl);
+                const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
+                lam[k][j] = -0.5f * (si * A - ci * B);
             }
         }
-        if (last) {
-            // lam_T from the final phases, whose (s, c) table is tab[p]
+        p ^= 1;
+    } else {
 #pragma unroll
-            for (int k = 0; k < kAdjQPT; ++k) {
-                const int m = threadIdx.x + k * kAdjTB;
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int m = threadIdx.x + k * kAdjTB;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int i = 4 * m + j;
-                    lam[k][j] = 0.f;
-                    if (m >= x.nq || i >= x.nb) continue;
-                    float A, B, Cl, Dl;
-                    gather<false>(g, tab(p), i, A, B, Cl, Dl);
-                    const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
-                    lam[k][j] = -0.5f * (si * A - ci * B);
-                }
-            }
-            p ^= 1;
+            for (int j = 0; j < 4; ++j) lam[k][j] = 0.f;
+            if (m >= x.nq) continue;
+            const float4 v = *reinterpret_cast<const float4*>(a.lam + slot_index(a, x, 0, 4 * m));
+            lam[k][0] = v.x;
+            lam[k][1] = v.y;
+            lam[k][2] = v.z;
+            lam[k][3] = v.w;
         }
-        // adjoint recurrence back through the segment
-        for (int s = t1 - 1; s >= t0; --s) {
-            load_words(a, x, a.seg, s - t0, u);
-            const uint32_t t = (uint32_t)(a.step0 + s);
+    }
+    for (int s = t1 - 1; s >= t0; --s) {
+        load_words(a, x, a.seg, s - t0, u);
+        const uint32_t t = (uint32_t)(a.step0 + s);
 #pragma unroll
-            for (int k = 0; k < kAdjQPT; ++k) {
-                const int m = threadIdx.x + k * kAdjTB;
-                if (m >= x.nq) break;
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int m = threadIdx.x + k * kAdjTB;
+            if (m >= x.nq) break;
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
-                    tab(p)[4 * m + j] = make_float4(si, ci, si * lam[k][j], ci * lam[k][j]);
-                }
+            for (int j = 0; j < 4; ++j) {
+                const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
+                tab(p)[4 * m + j] = make_float4(si, ci, si * lam[k][j], ci * lam[k][j]);
             }
-            __syncthreads();
-            const float Kt = a.K[s], Kst = a.Ks[s];
-            float gk = 0.f, gks = 0.f, gs = 0.f;
-#pragma unroll
-            for (int k = 0; k < kAdjQPT; ++k) {
-                const int m = threadIdx.x + k * kAdjTB;
-                if (m >= x.nq) break;
-                float z[4];
-                normals4((uint32_t)m, t, (uint32_t)x.b, x.k0, x.k1, z);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const int i = 4 * m + j;
-                    if (i >= x.nb) break;
-                    float A, B, Cl, Dl;
-                    gather<true>(g, tab(p), i, A, B, Cl, Dl);
-                    const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
-                    const float l = lam[k][j];
-                    const float csin = si * A - ci * B;
-                    const float ccos = ci * Cl + si * Dl - l * (ci * A + si * B);
-                    gk = __builtin_fmaf(l, csin, gk);
-                    gks = __builtin_fmaf(l, sin_q<QM>(si, ci, u[k][j], q), gks);
-                    gs = __builtin_fmaf(l, z[j], gs);
-                    lam[k][j] = l + a.dt * (Kt * ccos - (float)q * Kst * cos_q<QM>(si, ci, u[k][j], q) * l);
-                }
-            }
-            gk = wave_sum(gk);
-            gks = wave_sum(gks);
-            gs = wave_sum(gs);
-            if (lane == 0)
-                a.gpart[((size_t)s * nwg + x.wg) * kAdjWaves + wave] =
-                    make_float4(-a.dt * gk, -a.dt * gks, sqrt_dt * gs, 0.f);
-            p ^= 1;
         }
+        __syncthreads();
+        const float Kt = a.K[s], Kst = a.Ks[s];
+        float gk = 0.f, gks = 0.f, gs = 0.f;
+#pragma unroll
+        for (int k = 0; k < kAdjQPT; ++k) {
+            const int m = threadIdx.x + k * kAdjTB;
+            if (m >= x.nq) break;
+            float z[4];
+            normals4((uint32_t)m, t, (uint32_t)x.b, x.k0, x.k1, z);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int i = 4 * m + j;
+                if (i >= x.nb) break;
+                float A, B, Cl, Dl;
+                gather<true>(g, tab(p), i, A, B, Cl, Dl);
+                const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
+                const float l = lam[k][j];
+                const float csin = si * A - ci * B;
+                const float ccos = ci * Cl + si * Dl - l * (ci * A + si * B);
+                gk = __builtin_fmaf(l, csin, gk);
+                gks = __builtin_fmaf(l, sin_q<QM>(si, ci, u[k][j], q), gks);
+                gs = __builtin_fmaf(l, z[j], gs);
+                lam[k][j] = l + a.dt * (Kt * ccos - (float)q * Kst * cos_q<QM>(si, ci, u[k][j], q) * l);
+            }
+        }
+        gk = wave_sum(gk);
+        gks = wave_sum(gks);
+        gs = wave_sum(gs);
+        if (lane == 0)
+            a.gpart[((size_t)s * nwg + x.wg) * kAdjWaves + wave] =
+                make_float4(-a.dt * gk, -a.dt * gks, sqrt_dt * gs, 0.f);
+        p ^= 1;
+    }
+#pragma unroll
+    for (int k = 0; k < kAdjQPT; ++k) {
+        const int m = threadIdx.x + k * kAdjTB;
+        if (m >= x.nq) break;
+        *reinterpret_cast<float4*>(a.lam + slot_index(a, x, 0, 4 * m)) =
+            make_float4(lam[k][0], lam[k][1], lam[k][2], lam[k][3]);
     }
 }
 
@@ -695,12 +745,24 @@ AdjFn forward_fn(int q, int mode) {
     return f[qc][mode];
 }
 
-AdjFn backward_fn(int q, int mode) {
+AdjFn recompute_fn(int q, int mode) {
+    const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
+    static const AdjFn f[3][4] = {
+        {adjoint_recompute_kernel<0, 0>, adjoint_recompute_kernel<0, 1>,
+         adjoint_recompute_kernel<0, 2>, adjoint_recompute_kernel<0, 3>},
+        {adjoint_recompute_kernel<2, 0>, adjoint_recompute_kernel<2, 1>,
+         adjoint_recompute_kernel<2, 2>, adjoint_recompute_kernel<2, 3>},
+        {adjoint_recompute_kernel<3, 0>, adjoint_recompute_kernel<3, 1>,
+         adjoint_recompute_kernel<3, 2>, adjoint_recompute_kernel<3, 3>}};
+    return f[qc][mode];
+}
+
+AdjFn segment_fn(int q, int mode) {
     const int qc = q == 2 ? 1 : q == 3 ? 2 : 0;
     static const AdjFn f[3][3] = {
-        {adjoint_backward_kernel<0, 0>, adjoint_backward_kernel<0, 1>, adjoint_backward_kernel<0, 2>},
-        {adjoint_backward_kernel<2, 0>, adjoint_backward_kernel<2, 1>, adjoint_backward_kernel<2, 2>},
-        {adjoint_backward_kernel<3, 0>, adjoint_backward_kernel<3, 1>, adjoint_backward_kernel<3, 2>}};
+        {adjoint_segment_kernel<0, 0>, adjoint_segment_kernel<0, 1>, adjoint_segment_kernel<0, 2>},
+        {adjoint_segment_kernel<2, 0>, adjoint_segment_kernel<2, 1>, adjoint_segment_kernel<2, 2>},
+        {adjoint_segment_kernel<3, 0>, adjoint_segment_kernel<3, 1>, adjoint_segment_kernel<3, 2>}};
     return f[qc][mode];
 }
 
@@ -768,6 +830,46 @@ int launch_adjoint_forward(Problem* p, const oim_adjoint_cfg* cfg, const float* 
                       "adjoint_forward_kernel");
 }
 
+namespace {
+
+// The second stream and the events of the overlapped backward pass, made on
+// a problem's first backward call (default priority, non-blocking).
+int adjoint_streams(Problem* p) {
+    if (p->adj_stream) return OIM_OK;
+    hipError_t e = hipStreamCreateWithFlags(&p->adj_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+        p->adj_stream = nullptr;
+        return hip_error(e, "adjoint stream");
+    }
+    for (int k = 0; k < kAdjEvents; ++k) {
+        e = hipEventCreateWithFlags(&p->adj_ev[k], hipEventDisableTiming);
+        if (e != hipSuccess) {
+            p->adj_ev[k] = nullptr;
+            return hip_error(e, "adjoint events");
+        }
+    }
+    return OIM_OK;
+}
+
+}  // namespace
+
+void adjoint_release(Problem* p) {
+    if (p->adj_stream) {
+        (void)hipStreamSynchronize(p->adj_stream);
+        (void)hipStreamDestroy(p->adj_stream);
+        p->adj_stream = nullptr;
+    }
+    for (int k = 0; k < kAdjEvents; ++k) {
+        if (p->adj_ev[k]) (void)hipEventDestroy(p->adj_ev[k]);
+        p->adj_ev[k] = nullptr;
+    }
+}
+
+// Segments last first; segment sg's states live in buffer sg % 2.  The
+// recomputation runs on the problem's second stream, the adjoint on the
+// caller's: adjoint(sg) waits for recompute(sg), recompute(sg - 2) waits for
+// adjoint(sg) (the buffer it overwrites), so recompute(sg - 1) overlaps
+// adjoint(sg).  The caller's stream ends after every kernel of the pass.
 int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
                             const float* sigma, const uint64_t* seeds, int64_t step0,
                             const uint32_t* ckpt, double* gK, double* gKs, double* gS,
@@ -775,11 +877,13 @@ int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float*
     AdjArgs a = base_args(p, cfg, K, Ks, sigma, seeds, step0);
     if (cfg->steps == 0) return OIM_OK;
     const int nwg = cfg->R * p->n_inst;
-    const size_t seg_bytes = (size_t)cfg->checkpoint_every * cfg->R * a.P * sizeof(uint32_t);
+    auto up = [](size_t b) { return (b + 255) / 256 * 256; };
+    const size_t seg_bytes = up((size_t)(cfg->checkpoint_every + 1) * cfg->R * a.P * sizeof(uint32_t));
+    const size_t lam_bytes = up((size_t)cfg->R * a.P * sizeof(float));
     const size_t part_bytes = (size_t)cfg->steps * nwg * kAdjWaves * sizeof(float4);
-    const size_t need = seg_bytes + part_bytes + 256;
+    const size_t need = 2 * seg_bytes + lam_bytes + part_bytes + 256;
     if (p->adj_bytes < need) {
-        hipFree(p->d_adj);
+        (void)hipFree(p->d_adj);
         p->d_adj = nullptr;
         p->adj_bytes = 0;
         const hipError_t e = hipMalloc(&p->d_adj, need);
@@ -791,13 +895,37 @@ int launch_adjoint_backward(Problem* p, const oim_adjoint_cfg* cfg, const float*
         }
         p->adj_bytes = need;
     }
+    int st = adjoint_streams(p);
+    if (st) return st;
     unsigned char* w = static_cast<unsigned char*>(p->d_adj);
+    uint32_t* segbuf[2] = {reinterpret_cast<uint32_t*>(w), reinterpret_cast<uint32_t*>(w + seg_bytes)};
     a.ckpt = const_cast<uint32_t*>(ckpt);
-    a.seg = reinterpret_cast<uint32_t*>(w);
-    a.gpart = reinterpret_cast<float4*>(w + (seg_bytes + 255) / 256 * 256);
-    size_t lds = 0;
-    const int mode = csr_mode(p, a.tabN, &lds, false);
-    int st = launch_adj(backward_fn(cfg->q, mode), lds, nwg, stream, a, "adjoint_backward_kernel");
+    a.lam = reinterpret_cast<float*>(w + 2 * seg_bytes);
+    a.gpart = reinterpret_cast<float4*>(w + 2 * seg_bytes + lam_bytes);
+    size_t lds_rec = 0, lds_adj = 0;
+    const AdjFn frec = recompute_fn(cfg->q, csr_mode(p, a.tabN, &lds_rec, true));
+    const AdjFn fadj = segment_fn(cfg->q, csr_mode(p, a.tabN, &lds_adj, false));
+    hipStream_t side = p->adj_stream;
+    hipEvent_t* start = &p->adj_ev[0];
+    hipEvent_t* rec = &p->adj_ev[1];   // [2]
+    hipEvent_t* adj = &p->adj_ev[3];   // [2]
+    hipError_t e = hipEventRecord(*start, stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(side, *start, 0);
+    if (e != hipSuccess) return hip_error(e, "adjoint stream fork");
+    for (int sg = a.nseg - 1; sg >= 0 && !st; --sg) {
+        const int buf = sg & 1;
+        a.cur_seg = sg;
+        a.seg = segbuf[buf];
+        if (sg + 2 <= a.nseg - 1 && (e = hipStreamWaitEvent(side, adj[buf], 0)) != hipSuccess)
+            return hip_error(e, "adjoint buffer wait");
+        if ((st = launch_adj(frec, lds_rec, nwg, side, a, "adjoint_recompute_kernel"))) break;
+        if ((e = hipEventRecord(rec[buf], side)) != hipSuccess ||
+            (e = hipStreamWaitEvent(stream, rec[buf], 0)) != hipSuccess)
+            return hip_error(e, "adjoint segment order");
+        if ((st = launch_adj(fadj, lds_adj, nwg, stream, a, "adjoint_segment_kernel"))) break;
+        if ((e = hipEventRecord(adj[buf], stream)) != hipSuccess)
+            return hip_error(e, "adjoint segment order");
+    }
     if (st) return st;
     hipLaunchKernelGGL(adjoint_reduce_kernel, dim3((cfg->steps + 255) / 256), dim3(256), 0, stream,
                        a.gpart, cfg->steps, nwg * kAdjWaves, gK, gKs, gS);

@@ -45,6 +45,7 @@ void release(Problem* p) {
     hipFree(p->d_order);
     stepwise_release(p);
     hipFree(p->d_work);
+    adjoint_release(p);
     hipFree(p->d_adj);
     dense_release(p);
     unregister_problem(p);

@@ -85,9 +85,12 @@ struct Problem {
     int16_t tuned_ms[3] = {0, 0, 0};
     int16_t tuned_rpl[3] = {4, 4, 4};
 
-    // cached scratch of the adjoint backward pass
+    // cached scratch of the adjoint backward pass, and its second stream and
+    // events (start, recomputed[2], adjoint done[2])
     void* d_adj = nullptr;
     size_t adj_bytes = 0;
+    hipStream_t adj_stream = nullptr;
+    hipEvent_t adj_ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
 };
 
 // error plumbing (errors.cpp)
@@ -149,6 +152,8 @@ int tune_persistent(Problem* p, const oim_run_cfg* cfg, const float* K, const fl
                     int32_t trial_steps, oim_tune_report* rep, hipStream_t stream);
 int validate_adjoint_cfg(const Problem* p, const oim_adjoint_cfg* cfg);
 int64_t adjoint_checkpoint_words(const Problem* p, const oim_adjoint_cfg* cfg);
+constexpr int kAdjEvents = 5;
+void adjoint_release(Problem* p);
 int launch_adjoint_forward(Problem* p, const oim_adjoint_cfg* cfg, const float* K, const float* Ks,
                            const float* sigma, const uint64_t* seeds, int64_t step0,
                            const float* theta0, uint32_t* ckpt, float* thetaT, double* loss,
