@@ -430,9 +430,12 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
 def colouring_workload(args):
     """Batched Potts 3-colouring: 1024 planted 3-colourable graphs, n uniform in
     [100, 600] (seed 2), average degree 4.6, J = -1, q = 3, 5000 steps,
-    readout every 50 steps; all graphs in one launch of the LDS-resident
-    kernel against a plain loop of one launch per graph.  Target: >= 99 %
-    satisfied edges in every graph."""
+    readout every 50 steps; all graphs (R replicas each) in one launch of the
+    LDS-resident kernel against a plain loop of one launch per (graph,
+    replica).  The objective is the number of satisfied edges.  Two targets:
+    99 % of the best satisfied count known for each graph (the best over
+    every run of the campaign, as for max-cut), and 99 % of the planted
+    optimum (every edge satisfied)."""
     import torch
     import paper_2505_22631_amd as oim
     import synth
@@ -456,7 +459,6 @@ def colouring_workload(args):
     best_step = torch.empty(R * count, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     edges = np.array([g.nnz // 2 for g in graphs], np.float64)
-    target = np.floor(0.01 * edges)  # conflicts allowed per graph
     launch, _ = tune.tuned(prob, th_init, dK, dKs, dsg, seeds, q=q, dt=DT, trial_steps=500)
 
     def solve(ev):
@@ -470,40 +472,114 @@ def colouring_workload(args):
 
     wall_ms, run_ms = _timed_runs(solve, max(1, min(args.steps, 10)), args.warmup)
     eu = float(big.nnz) * R * steps
-    tr = trace.cpu().numpy().reshape(nr, R, count)             # conflicts per readout
-    best_graph = np.minimum.accumulate(tr.min(axis=1), axis=0)  # best over replicas so far
-    ok = best_graph <= target[None, :]
-    reached = ok[-1]
-    first = np.where(reached, np.argmax(ok, axis=0), -1)
-    t99 = (float(first.max() + 1) * M / steps * run_ms) if reached.all() else None
+    # satisfied edges per readout, best over the graph's replicas so far
+    # (the Eq. 2 energy of J = -1 is the number of conflicting edges)
+    sat = edges[None, :] - trace.cpu().numpy().reshape(nr, R, count).min(axis=1)
+    sat_so_far = np.maximum.accumulate(sat, axis=0)
 
-    # plain loop over a sample of the graphs (one problem, one launch each,
-    # the same R replicas of the graph)
+    # best known per graph: the timed solve, two more seed sets (also the
+    # restarts of the batch below) and one run four times as long, all untimed
+    best_known = sat_so_far[-1].copy()
+    launches = [sat_so_far]
+    for k in range(2):
+        th_k = torch.from_numpy(synth.theta0(R, big.n, seed=200 + k)).to(dev)
+        sd_k = torch.from_numpy(synth.seeds(R, (k + 1) * 1000003)).to(dev)
+        ro = oim.run(prob, th_k, dK, dKs, dsg, sd_k, q=q, dt=DT, readout_every=M)
+        c = ro["trace"].cpu().numpy().reshape(nr, R, count).min(axis=1)
+        launches.append(np.maximum.accumulate(edges[None, :] - c, axis=0))
+        best_known = np.maximum(best_known, launches[-1][-1])
+    lK, lKs, lsg, _, _ = synth.workload_schedule("colouring", prob.info["max_abs_row_sum"],
+                                                 4 * steps, DT)
+    th_l = torch.from_numpy(synth.theta0(R, big.n, seed=300)).to(dev)
+    ro = oim.run(prob, th_l, torch.from_numpy(lK).to(dev), torch.from_numpy(lKs).to(dev),
+                 torch.from_numpy(lsg).to(dev), torch.from_numpy(synth.seeds(R, 1 << 21)).to(dev),
+                 q=q, dt=DT, readout_every=M)
+    c = ro["trace"].cpu().numpy().reshape(-1, R, count).min(axis=(0, 1))
+    best_known = np.maximum(best_known, edges - c)
+    target_best = 0.99 * best_known
+    target_planted = 0.99 * edges
+    # further relaunches of the batch (other seeds, untimed, not counted in
+    # best_known) while some graph has not reached 99 % of its best known
+    max_launches = 8
+    k = len(launches)
+    while k < max_launches and not np.all(
+            np.max([l_[-1] for l_ in launches], axis=0) >= target_best):
+        th_k = torch.from_numpy(synth.theta0(R, big.n, seed=400 + k)).to(dev)
+        sd_k = torch.from_numpy(synth.seeds(R, (k + 7) * 1000003)).to(dev)
+        ro = oim.run(prob, th_k, dK, dKs, dsg, sd_k, q=q, dt=DT, readout_every=M)
+        c = ro["trace"].cpu().numpy().reshape(nr, R, count).min(axis=1)
+        launches.append(np.maximum.accumulate(edges[None, :] - c, axis=0))
+        k += 1
+
+    def t_all(target):
+        """Time until every graph has reached its target: a graph that
+        misses it in one launch of the batch is caught by the next launch
+        (other seeds), as the plain loop moves on to the graph's next
+        replica; None if some graph misses it in every launch.  Also the
+        graphs reaching it in the first launch."""
+        t_g = np.full(count, np.inf)
+        for k, sat_k in enumerate(launches):
+            ok = sat_k >= target[None, :]
+            hit = ok[-1] & ~np.isfinite(t_g)
+            first = np.argmax(ok, axis=0)
+            t_g[hit] = (k + (first[hit] + 1) * M / steps) * run_ms
+        first_launch = int(np.sum(launches[0][-1] >= target))
+        return (float(t_g.max()) if np.all(np.isfinite(t_g)) else None), first_launch
+
+    t99_best, reach_best = t_all(target_best)
+    t99_planted, reach_planted = t_all(target_planted)
+
+    # plain loop over a sample of the graphs: one problem per graph, one
+    # launch per replica (R = 1), replicas in turn until the graph reaches
+    # the target
     sample = min(args.plain_graphs, count)
     rng = np.random.default_rng(5)
     pick = np.sort(rng.choice(count, size=sample, replace=False))
-    per, hit_ms, sat = [], [], []
-    tr1 = torch.empty((nr, R), dtype=torch.float64, device=dev)
+    per, hit_best, hit_planted = [], [], []
+    tr1 = torch.empty((nr, 1), dtype=torch.float64, device=dev)
     for b in pick:
         g = graphs[b]
         with oim.Problem.from_csr(g.n, g.row_ptr, g.col, -np.ones(g.nnz, np.float32)) as p1:
             th1 = th_init[:, off[b]:off[b + 1]].contiguous()
-            oim.oim_run(p1.handle, g.n, th1.clone(), dK, dKs, dsg, seeds, q=q, dt=DT)  # warm
-            th1c = th1.clone()
+            oim.oim_run(p1.handle, g.n, th1[:1].clone(), dK, dKs, dsg, seeds[:1], q=q, dt=DT)
+            elapsed, hb, hp, best1 = 0.0, None, None, -np.inf
+            # replicas in turn (the batch's R, then further seeds, up to as
+            # many runs as the batch may use) until both targets are met
+            for r in range(max_launches * R):
+                if hb is not None and hp is not None:
+                    break
+                if r >= R and hb is not None:
+                    break
+                th1c = (th1[r:r + 1].clone() if r < R else torch.from_numpy(
+                    synth.theta0(1, g.n, seed=10_000 + r)).to(dev))
+                sd1 = seeds[r:r + 1] if r < R else torch.from_numpy(synth.seeds(1, 77_000 + r)).to(dev)
 
-            def one():
-                oim.oim_run(p1.handle, g.n, th1c, dK, dKs, dsg, seeds, q=q, dt=DT,
-                            readout_every=M, trace=tr1)
-            el = _sync_time(one)
-        per.append(el)
-        c = np.minimum.accumulate(tr1.cpu().numpy().min(axis=1))
-        h = np.nonzero(c <= target[b])[0]
-        sat.append(bool(h.size))
-        hit_ms.append((min((int(h[0]) + 1) * M, steps) / steps * el * 1e3) if h.size else None)
-    plain_ms_per_graph = float(np.mean(per)) * 1e3
-    plain_total_ms = plain_ms_per_graph * count
-    plain_t99 = (float(np.mean([x for x in hit_ms if x is not None])) * count
-                 if all(sat) else None)
+                def one():
+                    oim.oim_run(p1.handle, g.n, th1c, dK, dKs, dsg, sd1, q=q, dt=DT,
+                                readout_every=M, trace=tr1)
+                el = _sync_time(one)
+                per.append(el)
+                s1 = np.maximum(np.maximum.accumulate(edges[b] - tr1.cpu().numpy()[:, 0]), best1)
+                best1 = s1[-1]
+                for tgt, name in ((target_best[b], "b"), (target_planted[b], "p")):
+                    h = np.nonzero(s1 >= tgt)[0]
+                    if h.size and (hb if name == "b" else hp) is None:
+                        t = (elapsed + min((int(h[0]) + 1) * M, steps) / steps * el) * 1e3
+                        if name == "b":
+                            hb = t
+                        else:
+                            hp = t
+                elapsed += el
+        hit_best.append(hb)
+        hit_planted.append(hp)
+    plain_ms_per_run = float(np.mean(per)) * 1e3
+    plain_total_ms = plain_ms_per_run * count * R
+
+    def plain_t(hits):
+        return float(np.mean(hits)) * count if all(h is not None for h in hits) else None
+
+    plain_t99_best = plain_t(hit_best)
+    plain_t99_planted = plain_t(hit_planted)
     bps = sparse_bytes_per_step(big.n, big.nnz, R)
     roof = hbm_roofline(bps, steps, run_ms, "persistent_sparse_kernel",
                         {"launch": {"block": launch["block"],
@@ -520,13 +596,30 @@ def colouring_workload(args):
                    "replicas_per_graph": R, "n_total": big.n, "nnz": big.nnz, "em_steps": steps,
                    "q": q, "K_max": kmax, "Ks_max": ksmax, "readout_every": M},
         "roofline": roof,
-        "mean_satisfied_fraction_best_replica": float(np.mean(1.0 - best_graph[-1] / edges)),
-        "graphs_reaching_99pct": int(reached.sum()),
-        "time_to_99pct_satisfied_all_graphs_ms": t99,
-        "plain": {"ms_per_graph": plain_ms_per_graph, "total_ms_extrapolated": plain_total_ms,
-                  "time_to_99pct_all_graphs_ms_extrapolated": plain_t99,
-                  "graphs_timed": sample, "graphs_timed_reaching_99pct": int(sum(sat)),
-                  "eu_per_s": eu / (plain_total_ms * 1e-3)},
+        "mean_satisfied_fraction_best_replica": float(np.mean(sat_so_far[-1] / edges)),
+        "mean_satisfied_fraction_best_known": float(np.mean(best_known / edges)),
+        "graphs_reaching_99pct_best_known_first_launch": reach_best,
+        "time_to_99pct_best_known_all_graphs_ms": t99_best,
+        "graphs_reaching_99pct_planted_first_launch": reach_planted,
+        "time_to_99pct_planted_all_graphs_ms": t99_planted,
+        "time_to_target_note": "the batch is relaunched with other seeds while a graph misses "
+                               "the target (up to 8 launches), as the plain loop runs a graph's "
+                               "replicas in turn (up to 8 x R); null if some graph misses it",
+        "batch_launches_used": len(launches),
+        "best_known": "per graph: the most satisfied edges over the timed solve, two more "
+                      "seed sets and one run 4x as long (all untimed)",
+        "plain": {"ms_per_graph_replica_run": plain_ms_per_run,
+                  "total_ms_extrapolated": plain_total_ms,
+                  "time_to_99pct_best_known_all_graphs_ms_extrapolated": plain_t99_best,
+                  "time_to_99pct_planted_all_graphs_ms_extrapolated": plain_t99_planted,
+                  "graphs_timed": sample,
+                  "graphs_timed_reaching_99pct_best_known": int(sum(h is not None for h in hit_best)),
+                  "graphs_timed_reaching_99pct_planted": int(sum(h is not None for h in hit_planted)),
+                  "eu_per_s": eu / (plain_total_ms * 1e-3),
+                  "note": "one launch per (graph, replica), replicas in turn until the graph "
+                          "reaches the target; a sample of graphs, extrapolated to all"},
+        "speedup_time_to_99pct_best_known": (plain_t99_best / t99_best
+                                             if plain_t99_best and t99_best else None),
         "speedup_batched_vs_plain": plain_total_ms / wall_ms,
     }
     if not args.no_cpu_baseline:
@@ -844,7 +937,7 @@ def main():
     ap.add_argument("--dense-reps", type=int, default=5, help="timed dense solves")
     ap.add_argument("--plain-graphs", type=int, default=32,
                     help="graphs timed in the plain per-graph loop of the batched workloads")
-    ap.add_argument("--colour-replicas", type=int, default=1,
+    ap.add_argument("--colour-replicas", type=int, default=8,
                     help="replicas per graph in the colouring batch")
     ap.add_argument("--stepwise", type=int, default=1,
                     help="also time the torus solve on the stepwise hipGraph loop (0: skip)")
