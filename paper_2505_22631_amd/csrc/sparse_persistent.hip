@@ -101,9 +101,28 @@ __device__ __forceinline__ float2 sc_at(const unsigned char*, int byte_off) {
 template <int TB, int MS, int QM, int RPL>
 __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
-    // workgroup -> (instance, replica): all replicas of the largest instance first
-    const int inst_id = a.order[blockIdx.x / a.R];
-    const int r = blockIdx.x % a.R;
+    // workgroup -> (instance, replica).  Consecutive workgroup ids go to the
+    // 8 XCDs in turn, each with its own L2; the replicas of one instance are
+    // kept on one XCD (they read the same edge image every step) and the
+    // instances, largest first, are dealt to the XCDs in turn: XCD c takes
+    // instances c, c + 8, c + 16, ... of the order, all replicas of each
+    // before the next.  Instances past the last multiple of 8 follow in
+    // plain order.
+    int grp, r;
+    {
+        const int b = blockIdx.x;
+        const int I8 = a.I / 8 * 8;
+        const int head = a.R * I8;
+        if (b < head) {
+            const int c = b & 7, k = b >> 3;
+            grp = c + 8 * (k / a.R);
+            r = k % a.R;
+        } else {
+            grp = I8 + (b - head) / a.R;
+            r = (b - head) % a.R;
+        }
+    }
+    const int inst_id = a.order[grp];
     const int4 idesc = a.inst[inst_id];
     const int slice0 = idesc.x, S = idesc.y, off = idesc.z, n = idesc.w;
     const int plane = S * 64;
