@@ -202,7 +202,7 @@ int oim_run(oim_problem p, const oim_run_cfg* cfg, const float* K, const float* 
  * held until the process ends, and launch their per-step kernels directly
  * (no hipGraph is instantiated).  A run whose workspace exceeds the array is
  * rejected with OIM_E_UNSUPPORTED (the stepwise loop needs about
- * 20 * n * ceil(R / 64) * 64 bytes, the dense loop
+ * 8 * n * ceil(R / 64) * 64 bytes, the dense loop
  * 20 * ceil(n / 128) * 128 * ceil(R / 64) * 64 bytes); so is an FP32 run on
  * a dense problem whose FP32 image of J has not been made by an earlier
  * oim_run with OIM_PREC_FP32.  Every call on one device shares that device's

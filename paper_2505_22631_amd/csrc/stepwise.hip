@@ -2,13 +2,17 @@
 // kernel per Euler-Maruyama step, for replicas too large for the
 // LDS-resident kernel.
 //
-// Layout: replica index fastest, [n][Rp] (Rp = R rounded up to 64), for the
-// phase words and for two (sin, cos) tables (ping-pong: step t reads table
-// t%2 and writes table (t+1)%2, which keeps the synchronous update of
-// Algorithm 1).  A wave owns one quad (4 consecutive oscillators) and 64
-// replicas: CSR entries are wave-uniform (scalar loads) and each neighbour
-// gather is one coalesced 512-byte load.  Lane r draws the quad's four
-// normals with one Philox call keyed by replica r's seed.
+// Layout: replica index fastest, [n][Rp] (Rp = R rounded up to 64), two
+// buffers of phase words (ping-pong: step s reads buffer s % 2 and writes
+// buffer (s + 1) % 2, which keeps the synchronous update of Algorithm 1).
+// The state is the phase word alone (4 bytes per oscillator and replica):
+// the (sin, cos) of a neighbour is recomputed from its word where it is
+// gathered, the same function of the same word as anywhere else, so the
+// results equal the LDS-resident loop's bit for bit.  A wave owns one quad
+// (4 consecutive oscillators) and 64 replicas: CSR entries are wave-uniform
+// (scalar loads) and each neighbour gather is one coalesced 256-byte load.
+// Lane r draws the quad's four normals with one Philox call keyed by replica
+// r's seed.
 //
 // The step loop is a hipGraph of `chunk` step kernels plus a node that
 // advances a device-resident step base; the executable graph is replayed
@@ -57,9 +61,8 @@ struct StepArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const float* J;
-    uint32_t* U;          // [np][Rp]
-    const float2* tin;    // [np][Rp]
-    float2* tout;
+    const uint32_t* Uin;  // [np][Rp] phase words of step s
+    uint32_t* Uout;       // [np][Rp] phase words of step s + 1
     const CallArgs* call;
     int k;                // position of this node in the chunk
     int n, R, Rp, q;
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
 #pragma unroll
     for (int j = 0; j < 4; ++j) A0[j] = B0[j] = A1[j] = B1[j] = 0.f;
     for (int t = 0; t < lmax; t += 2) {
-        float2 p[4][2];
+        uint32_t p[4][2];
         float w[4][2];
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -135,14 +138,16 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
                 const int64_t e = ok ? eb[j] + t + h : 0;
                 const int c = ok ? a.col[e] : 4 * m;
                 w[j][h] = ok ? a.J[e] : 0.f;
-                p[j][h] = a.tin[(size_t)c * Rp + r];
+                p[j][h] = a.Uin[(size_t)c * Rp + r];
             }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-            A0[j] = __builtin_fmaf(w[j][0], p[j][0].y, A0[j]);
-            B0[j] = __builtin_fmaf(w[j][0], p[j][0].x, B0[j]);
-            A1[j] = __builtin_fmaf(w[j][1], p[j][1].y, A1[j]);
-            B1[j] = __builtin_fmaf(w[j][1], p[j][1].x, B1[j]);
+            const float s0 = sin_turn(p[j][0]), c0 = cos_turn(p[j][0]);
+            const float s1 = sin_turn(p[j][1]), c1 = cos_turn(p[j][1]);
+            A0[j] = __builtin_fmaf(w[j][0], c0, A0[j]);
+            B0[j] = __builtin_fmaf(w[j][0], s0, B0[j]);
+            A1[j] = __builtin_fmaf(w[j][1], c1, A1[j]);
+            B1[j] = __builtin_fmaf(w[j][1], s1, B1[j]);
         }
     }
 #pragma unroll
@@ -150,14 +155,12 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
         const int i = 4 * m + j;
         if (i >= a.n) break;
         const size_t idx = (size_t)i * Rp + r;
-        const float2 own = a.tin[idx];
+        const uint32_t u0 = a.Uin[idx];
+        const float os = sin_turn(u0), oc = cos_turn(u0);
         const float A = A0[j] + A1[j], B = B0[j] + B1[j];
-        const float coup = own.x * A - own.y * B;
-        const uint32_t u0 = a.U[idx];
-        const float drift = kc * coup + ks * sin_q<QM>(own.x, own.y, u0, q);
-        const uint32_t u = advance(u0, __builtin_fmaf(ns, z[j], drift));
-        a.U[idx] = u;
-        a.tout[idx] = make_float2(sin_turn(u), cos_turn(u));
+        const float coup = os * A - oc * B;
+        const float drift = kc * coup + ks * sin_q<QM>(os, oc, u0, q);
+        a.Uout[idx] = advance(u0, __builtin_fmaf(ns, z[j], drift));
     }
 }
 
@@ -165,10 +168,10 @@ __global__ void advance_base_kernel(CallArgs* call, int chunk) { call->base += c
 
 __global__ void set_call_kernel(CallArgs* call, CallArgs v) { *call = v; }
 
-// [R][n] theta or phase words -> [np][Rp] phase words and table (both
-// tables get the initial values so padding is finite everywhere).
+// [R][n] theta or phase words -> [np][Rp] phase words (both buffers, so the
+// padding rows and replicas hold defined words everywhere).
 __global__ __launch_bounds__(256) void stepwise_init_kernel(const float* theta, const uint32_t* phase,
-                                                            uint32_t* U, float2* t0, float2* t1,
+                                                            uint32_t* U0, uint32_t* U1,
                                                             int n, int R, int np, int Rp) {
     const size_t total = (size_t)np * Rp;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -179,10 +182,8 @@ __global__ __launch_bounds__(256) void stepwise_init_kernel(const float* theta, 
             const size_t src = (size_t)r * n + i;
             u = phase ? phase[src] : phase_from_theta(theta[src]);
         }
-        U[e] = u;
-        const float2 v = make_float2(sin_turn(u), cos_turn(u));
-        t0[e] = v;
-        t1[e] = v;
+        U0[e] = u;
+        U1[e] = u;
     }
 }
 
@@ -388,7 +389,7 @@ Shape shape_of(const Problem* p, const oim_run_cfg* cfg) {
     int chunk = std::min(sh.steps, 64);
     if (sh.M > 0) chunk = std::max(1, (std::min(sh.steps, std::max(64, sh.M)) / sh.M)) * sh.M;
     sh.chunk = std::max(1, std::min(chunk, sh.steps));
-    sh.args_off = (sh.cells * (4 + 8 + 8) + (size_t)sh.gx * sh.Rp * 8 + (size_t)sh.R * 12 + 255) &
+    sh.args_off = (sh.cells * (4 + 4) + (size_t)sh.gx * sh.Rp * 8 + (size_t)sh.R * 12 + 255) &
                   ~(size_t)255;
     sh.bytes = sh.args_off + 256;
     return sh;
@@ -411,10 +412,9 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
         if (!p->step_plans) return set_error(OIM_E_NOMEM, "plan cache");
     }
     unsigned char* w = static_cast<unsigned char*>(work);
-    uint32_t* U = reinterpret_cast<uint32_t*>(w);
-    float2* T0 = reinterpret_cast<float2*>(w + cells * 4);
-    float2* T1 = T0 + cells;
-    double* part = reinterpret_cast<double*>(T1 + cells);
+    uint32_t* U0 = reinterpret_cast<uint32_t*>(w);
+    uint32_t* U1 = U0 + cells;
+    double* part = reinterpret_cast<double*>(U1 + cells);
     double* best = part + (size_t)gx * Rp;
     int32_t* best_at = reinterpret_cast<int32_t*>(best + R);
     CallArgs* call = reinterpret_cast<CallArgs*>(w + args_off);
@@ -435,8 +435,8 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     hipLaunchKernelGGL(set_call_kernel, dim3(1), dim3(1), 0, stream, call, ca);
     int st = check_launch("set_call_kernel");
     if (st) return st;
-    hipLaunchKernelGGL(stepwise_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U, T0,
-                       T1, n, R, np, Rp);
+    hipLaunchKernelGGL(stepwise_init_kernel, dim3(2048), dim3(256), 0, stream, theta, phase, U0, U1,
+                       n, R, np, Rp);
     if ((st = check_launch("stepwise_init_kernel"))) return st;
 
     using StepFn = void (*)(StepArgs);
@@ -446,18 +446,20 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     sa.row_ptr = p->d_row_ptr;
     sa.col = p->d_col;
     sa.J = p->d_J;
-    sa.U = U;
     sa.call = call;
     sa.n = n;
     sa.R = R;
     sa.Rp = Rp;
     sa.q = cfg->q;
     sa.gx = gx;
-    ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, U, part, call, 0, n, Rp, cfg->q};
+    // the state after local step s is in buffer (s + 1) % 2; after the run,
+    // in buffer steps % 2
+    uint32_t* const Ufinal = (steps & 1) ? U1 : U0;
+    ReadArgs ra{p->d_row_ptr, p->d_col, p->d_J, Ufinal, part, call, 0, n, Rp, cfg->q};
     BestArgs ba{};
     ba.part = part;
     ba.nblocks = gx;
-    ba.U = U;
+    ba.U = Ufinal;
     ba.best = best;
     ba.best_at = best_at;
     ba.call = call;
@@ -468,13 +470,16 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     ba.q = cfg->q;
 
     // Record one chunk: step kernels (with readouts where due) and the base
-    // advance.  Table parity alternates per step; an odd chunk flips it from
-    // one replay to the next, so it has a graph for each parity.
+    // advance.  Buffer parity alternates per step (step s reads buffer s % 2);
+    // an odd chunk flips it from one replay to the next, so it has a graph
+    // for each parity.
     auto record_chunk = [&](hipStream_t s, bool parity) -> int {
         for (int k = 0; k < chunk; ++k) {
             const bool odd = ((k & 1) != 0) != parity;
-            sa.tin = odd ? T1 : T0;
-            sa.tout = odd ? T0 : T1;
+            sa.Uin = odd ? U1 : U0;
+            sa.Uout = odd ? U0 : U1;
+            ra.U = sa.Uout;
+            ba.U = sa.Uout;
             sa.k = k;
             hipLaunchKernelGGL(fn, dim3(gx * (Rp / 64)), dim3(256), 0, s, sa);
             int rc = check_launch("stepwise_step_kernel");
@@ -568,8 +573,10 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     if (M > 0 && steps % M != 0) {
         ReadArgs rl = ra;
         rl.k = -1;
+        rl.U = Ufinal;
         BestArgs bl = ba;
         bl.k = -1;
+        bl.U = Ufinal;
         hipLaunchKernelGGL(stepwise_readout_kernel, dim3(gx, Rp / 64), dim3(256), 0, stream, rl);
         if ((st = check_launch("stepwise_readout_kernel"))) return st;
         hipLaunchKernelGGL(stepwise_best_kernel, dim3(R), dim3(256), 0, stream, bl);
@@ -585,7 +592,8 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
             if (e != hipSuccess) return hip_error(e, "best_step copy");
         }
     }
-    hipLaunchKernelGGL(stepwise_final_kernel, dim3(2048), dim3(256), 0, stream, U, theta, phase, n, R, Rp);
+    hipLaunchKernelGGL(stepwise_final_kernel, dim3(2048), dim3(256), 0, stream, Ufinal, theta, phase,
+                       n, R, Rp);
     return check_launch("stepwise_final_kernel");
 }
 

@@ -95,7 +95,7 @@ def test_workspace_beyond_the_array_is_rejected(oim):
     limit = oim.oim_noalloc_scratch_bytes()
     assert limit == 64 << 20
     g = synth.torus(100, 100, seed=1, signed=True)
-    R = 512  # 20 bytes x 10000 x 512 > 64 MiB
+    R = 1024  # 8 bytes x 10000 x 1024 > 64 MiB
     with oim.Problem.from_csr(g.n, g.row_ptr, g.col, (-g.w).astype(np.float32)) as prob:
         th = _t(synth.theta0(R, g.n, seed=1))
         before = th.clone()
