@@ -366,26 +366,29 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
     sw = None
     if stepwise:
         th_s = th_init.clone()
+        sw_steps = min(steps, args.stepwise_steps or steps)
 
         def solve_sw(ev):
             th_s.copy_(th_init)
             if ev:
                 ev[0].record(stream)
-            oim.oim_run(prob.handle, g.n, th_s, dK, dKs, dsg, seeds, q=q, dt=DT,
-                        readout_every=M, trace=trace, flags=oim.OIM_LOOP_STEPWISE)
+            oim.oim_run(prob.handle, g.n, th_s, dK[:sw_steps], dKs[:sw_steps], dsg[:sw_steps],
+                        seeds, q=q, dt=DT, readout_every=M,
+                        trace=trace[:oim.n_readouts(sw_steps, M)], flags=oim.OIM_LOOP_STEPWISE)
             if ev:
                 ev[1].record(stream)
         sw_wall, sw_ms = _timed_runs(solve_sw, max(1, min(3, timed_steps)), 1)
-        sw = {"ms_per_solve": sw_ms, "wall_ms_per_solve": sw_wall,
-              "eu_per_s": eu_per_solve / (sw_ms * 1e-3),
-              "slowdown_vs_lds_resident": sw_ms / kern_ms,
-              "roofline": hbm_roofline(sparse_bytes_per_step(g.n, g.nnz, R), steps, sw_ms,
+        sw = {"em_steps": sw_steps, "ms_per_solve": sw_ms, "wall_ms_per_solve": sw_wall,
+              "eu_per_s": eu_per_solve * sw_steps / steps / (sw_ms * 1e-3),
+              "slowdown_vs_lds_resident": sw_ms / (kern_ms * sw_steps / steps),
+              "roofline": hbm_roofline(sparse_bytes_per_step(g.n, g.nnz, R), sw_steps, sw_ms,
                                        "stepwise_step_kernel (hipGraph loop)")}
 
     roof = hbm_roofline(sparse_bytes_per_step(g.n, g.nnz, R), steps, kern_ms,
                         "persistent_sparse_kernel",
                         {"launch": {"block": launch["block"],
-                                    "slices_per_wave": launch["slices_per_wave"]}})
+                                    "slices_per_wave": launch["slices_per_wave"],
+                                    "rows_per_lane": launch.get("rows_per_lane", 4)}})
     prof = name if name in PROFILES else None
     if prof:
         roof["traffic"] = _profile_value(prof, f"traffic_bytes_per_launch_R{R}")
@@ -583,7 +586,8 @@ def colouring_workload(args):
     bps = sparse_bytes_per_step(big.n, big.nnz, R)
     roof = hbm_roofline(bps, steps, run_ms, "persistent_sparse_kernel",
                         {"launch": {"block": launch["block"],
-                                    "slices_per_wave": launch["slices_per_wave"]}})
+                                    "slices_per_wave": launch["slices_per_wave"],
+                                    "rows_per_lane": launch.get("rows_per_lane", 4)}})
     roof["traffic"] = _profile_value("colouring", f"traffic_bytes_per_launch_R{R}")
     valu = _profile_value("colouring", f"valu_busy_frac_R{R}")
     if valu is not None:
@@ -895,7 +899,8 @@ def sweep_workload(args):
         "config": {"workload": "schedule sweep on the 100x100 +-1 torus: 8 x 8 (K_max, Ks_max) "
                                "grid x 4 replicas, per-replica schedules, one launch",
                    "replicas": R, "em_steps": steps, "K_multipliers": kg, "Ks_multipliers": ksg},
-        "launch": {"block": launch["block"], "slices_per_wave": launch["slices_per_wave"]},
+        "launch": {"block": launch["block"], "slices_per_wave": launch["slices_per_wave"],
+                   "rows_per_lane": launch.get("rows_per_lane", 4)},
         "best_cut_grid": grid.tolist(),
         "best_cell": {"K_mult": kg[bi], "Ks_mult": ksg[bj], "cut": float(grid[bi, bj])},
         "plain": {"ms_per_cell": float(np.mean(per)) * 1e3, "ms_total_extrapolated":
@@ -941,6 +946,9 @@ def main():
                     help="replicas per graph in the colouring batch")
     ap.add_argument("--stepwise", type=int, default=1,
                     help="also time the torus solve on the stepwise hipGraph loop (0: skip)")
+    ap.add_argument("--stepwise-steps", type=int, default=0,
+                    help="EM steps of the stepwise solve (0: the whole schedule; fewer for "
+                         "counter runs, which serialise every step kernel)")
     ap.add_argument("--ref-mult", type=int, default=10,
                     help="length multiple of the untimed reference run that sets best_ref")
     args = ap.parse_args()
