@@ -19,17 +19,19 @@ using namespace oim;
 
 namespace {
 
+// count elements from the host, followed by `pad` zero elements.
 template <typename T>
-int dev_upload(T** dst, const T* src, size_t count, const char* what) {
+int dev_upload(T** dst, const T* src, size_t count, const char* what, size_t pad = 0) {
     *dst = nullptr;
-    if (count == 0) return OIM_OK;
-    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), count * sizeof(T));
+    if (count + pad == 0) return OIM_OK;
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(dst), (count + pad) * sizeof(T));
     if (e != hipSuccess) {
         *dst = nullptr;
         if (e == hipErrorOutOfMemory) return set_error(OIM_E_NOMEM, std::string(what) + ": out of device memory");
         return hip_error(e, what);
     }
-    e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (count) e = hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice);
+    if (e == hipSuccess && pad) e = hipMemset(*dst + count, 0, pad * sizeof(T));
     if (e != hipSuccess) return hip_error(e, what);
     return OIM_OK;
 }
@@ -156,10 +158,14 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     p->sell_slices = img.slices;
     p->max_slices = img.max_slices;
     p->sell_entries = (int64_t)img.entries.size();
+    // row_ptr with kCsrPad more copies of nnz: rows past n are empty
+    std::vector<int64_t> row_ptr_padded(row_ptr, row_ptr + (size_t)n + 1);
+    row_ptr_padded.resize((size_t)n + 1 + kCsrPad, nnz);
     if ((st = current_device(&p->device)) ||
-        (st = dev_upload(&p->d_row_ptr, row_ptr, (size_t)n + 1, "upload row_ptr")) ||
-        (st = dev_upload(&p->d_col, col_idx, (size_t)nnz, "upload col_idx")) ||
-        (st = dev_upload(&p->d_J, J, (size_t)nnz, "upload J")) ||
+        (st = dev_upload(&p->d_row_ptr, row_ptr_padded.data(), row_ptr_padded.size(),
+                         "upload row_ptr")) ||
+        (st = dev_upload(&p->d_col, col_idx, (size_t)nnz, "upload col_idx", kCsrPad)) ||
+        (st = dev_upload(&p->d_J, J, (size_t)nnz, "upload J", kCsrPad)) ||
         (st = dev_upload(&p->d_sell_desc, img.desc.data(), img.desc.size(), "upload slices")) ||
         (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell")) ||
         (st = dev_upload(&p->d_inst, img.inst.data(), img.inst.size(), "upload instances")) ||

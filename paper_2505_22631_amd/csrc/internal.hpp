@@ -36,6 +36,8 @@ struct SellImage {
     int32_t max_slices = 0;
 };
 
+constexpr size_t kCsrPad = 4;
+
 struct Problem {
     uint64_t handle = 0;  // registry key, the value callers hold as oim_problem
     int device = 0;
@@ -46,7 +48,11 @@ struct Problem {
     double max_abs_row_sum = 0.0;
     double sum_J_upper = 0.0;
 
-    // device: original CSR (sparse problems), for the readouts
+    // device: original CSR (sparse problems), for the readouts and the
+    // stepwise loop.  row_ptr is followed by kCsrPad copies of nnz (rows
+    // n .. n + 3 are empty, so the bounds of any quad's rows are in bounds),
+    // col and J by kCsrPad zero entries (a group of 4 consecutive entries
+    // starting at any index <= nnz is in bounds)
     int64_t* d_row_ptr = nullptr;
     int32_t* d_col = nullptr;
     float* d_J = nullptr;

@@ -30,6 +30,7 @@
 #include <algorithm>
 #include <cmath>
 #include <new>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "noise.hpp"
@@ -58,9 +59,10 @@ struct CallArgs {
 };
 
 struct StepArgs {
-    const int64_t* row_ptr;
-    const int32_t* col;
-    const float* J;
+    const int64_t* row_ptr;  // n + 1 entries and 4 copies of nnz
+    const int32_t* col;   // nnz entries and 4 zero entries of padding
+    const float* J;       // the same
+    int64_t nnz;
     const uint32_t* Uin;  // [np][Rp] phase words of step s
     uint32_t* Uout;       // [np][Rp] phase words of step s + 1
     const CallArgs* call;
@@ -84,11 +86,16 @@ __device__ __forceinline__ void step_block(int b, int nb, int gx, int& qb, int& 
     qb = t - rb * gx;
 }
 
+// A pointer read from the per-call block, as a global-memory pointer (such a
+// pointer is generic to the compiler, which would otherwise load through it
+// with flat instructions).
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
+
 template <int QM>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
-    const CallArgs& c = *a.call;
-    const int s = c.base + a.k;
-    if (s >= c.steps) return;
     const int lane = threadIdx.x & 63;
     int qb, rb;
     step_block(blockIdx.x, gridDim.x, a.gx, qb, rb);
@@ -96,71 +103,145 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     if (4 * m >= a.n) return;
     const int r = rb * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
-    const uint32_t t = (uint32_t)(c.step0 + s);
-    const float dt = c.dt;
-    const float sqrt_dt = __builtin_sqrtf(dt);
-    const int64_t so = (int64_t)(r < a.R ? r : 0) * c.sched_stride + s;
-    const float kc = -dt * c.K[so] * kTurnScale;
-    const float ks = -dt * c.Ks[so] * kTurnScale;
-    const float ns = c.sigma[so] * sqrt_dt * kTurnScale;
-    const uint64_t seed = r < a.R ? c.seeds[r] : 0ull;
-    float z[4];
-    normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
-    // The quad's four rows are walked in lock-step, two edges of each per
-    // iteration, so eight neighbour loads are in flight together.  Row
-    // lengths are wave-uniform (every lane is a replica of the same quad), so
-    // a row that is shorter than the longest costs only its idle slots, which
-    // load the quad's own entry with weight 0 and leave the sums unchanged
-    // (the table holds finite values).  Each row keeps its order: edges at
-    // even offsets into one partial sum, odd ones into the other.
+    const int rs = r < a.R ? r : a.R - 1;  // padding lanes borrow a replica's entries
+    // Every load of a step is issued up front, in three waves with one wait
+    // each: the per-call block, the quad's row bounds and its own words;
+    // then the schedule entries, the seed and the first group of each row's
+    // entries; then the neighbours' words.  Nothing before the store depends
+    // on whether this node's step is still part of the run (a node past the
+    // last step computes on local step 0's entries and writes nothing), and
+    // no select or branch depends on a loaded value, so the compiler keeps
+    // the loads together.
+    const CallArgs& c = *a.call;
+    int base = c.base, steps = c.steps, stride = c.sched_stride;
+    int64_t step0 = c.step0;
+    float dt = c.dt;
+    const float* Kp = c.K;
+    const float* Ksp = c.Ks;
+    const float* sgp = c.sigma;
+    const uint64_t* seedp = c.seeds;
+    int64_t rp[5];  // row_ptr carries 4 entries of padding (empty rows)
+#pragma unroll
+    for (int j = 0; j < 5; ++j) rp[j] = a.row_ptr[4 * m + j];
+    // one wait for the per-call block and the row bounds together: every
+    // use of them goes through this statement
+    asm(""
+        : "+s"(base), "+s"(steps), "+s"(stride), "+s"(step0), "+s"(dt), "+s"(Kp),
+                   "+s"(Ksp), "+s"(sgp), "+s"(seedp), "+s"(rp[0]), "+s"(rp[1]), "+s"(rp[2]),
+                   "+s"(rp[3]), "+s"(rp[4]));
+    const int s_node = base + a.k;
+    const bool live = s_node < steps;
+    const int s = live ? s_node : 0;
+    const uint32_t t = (uint32_t)(step0 + s);
+    const int64_t so = (int64_t)rs * stride + s;
+    const float Kv = global_ptr(Kp)[so];
+    const float Ksv = global_ptr(Ksp)[so];
+    const float sgv = global_ptr(sgp)[so];
+    const uint64_t seed = global_ptr(seedp)[rs];
     int64_t eb[4];
     int len[4];
     int lmax = 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-        const int i = 4 * m + j;
-        const bool ok = i < a.n;
-        eb[j] = ok ? a.row_ptr[i] : 0;
-        len[j] = ok ? (int)(a.row_ptr[i + 1] - eb[j]) : 0;
+        eb[j] = rp[j];
+        len[j] = (int)(rp[j + 1] - rp[j]);
         lmax = len[j] > lmax ? len[j] : lmax;
     }
-    float A0[4], B0[4], A1[4], B1[4];
+    uint32_t u0[4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) A0[j] = B0[j] = A1[j] = B1[j] = 0.f;
-    for (int t = 0; t < lmax; t += 2) {
-        uint32_t p[4][2];
-        float w[4][2];
+    for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
+    // The quad's four rows are walked in lock-step, four entries of each
+    // per group, so sixteen neighbour loads are in flight together.  Row
+    // lengths are wave-uniform (every lane is a replica of the same quad), so
+    // a row shorter than the longest costs only its idle slots.  Group t of
+    // row j is the 4 entries from eb + t, clamped to nnz (the arrays carry 4
+    // zero entries past the end, so a group is always in bounds and its
+    // column indexes valid); a slot past the row's end gets weight 0 by
+    // masking its bits, which leaves the sums unchanged (the words are
+    // finite).  Each row keeps its order: entries at even offsets into one
+    // partial sum, odd ones into the other.
+    uint32_t p[4][4];
+    float w[4][4];
+    auto gather = [&](int g, auto first) {
+        int ci[4][4];
+        uint32_t wb[4][4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t base = eb[j] + g;
+            base = base < a.nnz ? base : a.nnz;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                wb[j][h] = __float_as_uint(a.J[base + h]);
+                ci[j][h] = a.col[base + h];
+            }
+        }
+        // The first group's four rows' entry loads (scalar loads) are all
+        // issued before the first use: the loaded values pass through empty
+        // asm statements that no load may cross, so nothing that uses them
+        // is scheduled between the loads (each use of a scalar load waits
+        // for all of them).  Later groups are read with vector loads, which
+        // complete in order, and need no such help.
+        if constexpr (decltype(first)::value) {
+            asm(""
+                : "+s"(ci[0][0]), "+s"(ci[0][1]), "+s"(ci[0][2]), "+s"(ci[0][3]),
+                  "+s"(ci[1][0]), "+s"(ci[1][1]), "+s"(ci[1][2]), "+s"(ci[1][3]),
+                  "+s"(ci[2][0]), "+s"(ci[2][1]), "+s"(ci[2][2]), "+s"(ci[2][3]),
+                  "+s"(ci[3][0]), "+s"(ci[3][1]), "+s"(ci[3][2]), "+s"(ci[3][3]),
+                  "+s"(wb[0][0]), "+s"(wb[0][1]), "+s"(wb[0][2]), "+s"(wb[0][3]),
+                  "+s"(wb[1][0]), "+s"(wb[1][1]), "+s"(wb[1][2]), "+s"(wb[1][3]),
+                  "+s"(wb[2][0]), "+s"(wb[2][1]), "+s"(wb[2][2]), "+s"(wb[2][3]),
+                  "+s"(wb[3][0]), "+s"(wb[3][1]), "+s"(wb[3][2]), "+s"(wb[3][3]));
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                const bool ok = t + h < len[j];
-                const int64_t e = ok ? eb[j] + t + h : 0;
-                const int c = ok ? a.col[e] : 4 * m;
-                w[j][h] = ok ? a.J[e] : 0.f;
-                p[j][h] = a.Uin[(size_t)c * Rp + r];
+            for (int h = 0; h < 4; ++h) {
+                p[j][h] = a.Uin[(size_t)ci[j][h] * Rp + r];
+                const uint32_t keep = 0u - (uint32_t)(g + h < len[j]);
+                w[j][h] = __uint_as_float(wb[j][h] & keep);
             }
+    };
+    float A0[4], B0[4], A1[4], B1[4];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const float s0 = sin_turn(p[j][0]), c0 = cos_turn(p[j][0]);
-            const float s1 = sin_turn(p[j][1]), c1 = cos_turn(p[j][1]);
-            A0[j] = __builtin_fmaf(w[j][0], c0, A0[j]);
-            B0[j] = __builtin_fmaf(w[j][0], s0, B0[j]);
-            A1[j] = __builtin_fmaf(w[j][1], c1, A1[j]);
-            B1[j] = __builtin_fmaf(w[j][1], s1, B1[j]);
-        }
+    for (int j = 0; j < 4; ++j) A0[j] = B0[j] = A1[j] = B1[j] = 0.f;
+    auto accumulate = [&]() {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int h = 0; h < 4; h += 2) {
+                const float s0 = sin_turn(p[j][h]), c0 = cos_turn(p[j][h]);
+                const float s1 = sin_turn(p[j][h + 1]), c1 = cos_turn(p[j][h + 1]);
+                A0[j] = __builtin_fmaf(w[j][h], c0, A0[j]);
+                B0[j] = __builtin_fmaf(w[j][h], s0, B0[j]);
+                A1[j] = __builtin_fmaf(w[j][h + 1], c1, A1[j]);
+                B1[j] = __builtin_fmaf(w[j][h + 1], s1, B1[j]);
+            }
+    };
+    gather(0, std::true_type{});
+    // the quad's normals while the neighbour loads are in flight
+    float z[4];
+    normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
+    // pin the normals here (left alone, the compiler sinks them to the
+    // update, after the last neighbour load has returned)
+    asm volatile("" ::"v"(z[0]), "v"(z[1]), "v"(z[2]), "v"(z[3]) : "memory");
+    accumulate();
+    for (int g = 4; g < lmax; g += 4) {
+        gather(g, std::false_type{});
+        accumulate();
     }
+    if (!live) return;
+    const float kc = -dt * Kv * kTurnScale;
+    const float ks = -dt * Ksv * kTurnScale;
+    const float ns = sgv * __builtin_sqrtf(dt) * kTurnScale;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         const int i = 4 * m + j;
         if (i >= a.n) break;
-        const size_t idx = (size_t)i * Rp + r;
-        const uint32_t u0 = a.Uin[idx];
-        const float os = sin_turn(u0), oc = cos_turn(u0);
+        const float os = sin_turn(u0[j]), oc = cos_turn(u0[j]);
         const float A = A0[j] + A1[j], B = B0[j] + B1[j];
         const float coup = os * A - oc * B;
-        const float drift = kc * coup + ks * sin_q<QM>(os, oc, u0, q);
-        a.Uout[idx] = advance(u0, __builtin_fmaf(ns, z[j], drift));
+        const float drift = kc * coup + ks * sin_q<QM>(os, oc, u0[j], q);
+        a.Uout[(size_t)i * Rp + r] = advance(u0[j], __builtin_fmaf(ns, z[j], drift));
     }
 }
 
@@ -446,6 +527,7 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     sa.row_ptr = p->d_row_ptr;
     sa.col = p->d_col;
     sa.J = p->d_J;
+    sa.nnz = p->nnz;
     sa.call = call;
     sa.n = n;
     sa.R = R;
