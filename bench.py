@@ -48,8 +48,12 @@ SPARSE_SOURCES = ["paper_2505_22631_amd/csrc/sparse_persistent.hip",
                   "paper_2505_22631_amd/csrc/tree.hpp"]
 DENSE_SOURCES = ["paper_2505_22631_amd/csrc/dense.hip", "paper_2505_22631_amd/csrc/noise.hpp",
                  "paper_2505_22631_amd/csrc/phase.hpp"]
+STEPWISE_SOURCES = ["paper_2505_22631_amd/csrc/stepwise.hip",
+                    "paper_2505_22631_amd/csrc/noise.hpp", "paper_2505_22631_amd/csrc/phase.hpp",
+                    "paper_2505_22631_amd/csrc/tree.hpp"]
 PROFILES = {
     "torus": ("profiles/persistent_sparse_kernel__torus100x100_R256.md", SPARSE_SOURCES),
+    "stepwise": ("profiles/stepwise_step_kernel__torus100x100_R256.md", STEPWISE_SOURCES),
     "gnp800": ("profiles/persistent_sparse_kernel__gnp800_R256.md", SPARSE_SOURCES),
     "colouring": ("profiles/persistent_sparse_kernel__colouring1024_q3.md", SPARSE_SOURCES),
     "sk4096": ("profiles/dense_step_kernel__sk4096_R512.md", DENSE_SOURCES),
@@ -122,13 +126,19 @@ def oracle_baseline(run_sample, unit_eu, what, target_1t=4.0, target_nt=6.0):
     """Times the oracle as it stands on a bounded sample of a workload: once on
     one thread and once on every thread this process may use.
     run_sample(replicas, steps, threads) runs the sample; unit_eu is the
-    edge-updates of one replica-step.  Returns the cpu_baseline object."""
+    edge-updates of one replica-step; a sample longer than the schedule
+    (what["max_steps"]) runs the schedule again from its start as many times
+    as it takes.  Returns the cpu_baseline object."""
     cpu = host_cpu()
     N = cpu["threads_used"]
+    cap = int(what.get("max_steps", 1 << 62))
 
     def timed(R, steps, threads):
         t0 = time.perf_counter()
-        run_sample(R, steps, threads)
+        left = steps
+        while left > 0:
+            run_sample(R, min(left, cap), threads)
+            left -= min(left, cap)
         return time.perf_counter() - t0
 
     # one thread, one replica
@@ -383,6 +393,9 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
               "slowdown_vs_lds_resident": sw_ms / (kern_ms * sw_steps / steps),
               "roofline": hbm_roofline(sparse_bytes_per_step(g.n, g.nnz, R), sw_steps, sw_ms,
                                        "stepwise_step_kernel (hipGraph loop)")}
+        if name == "torus":
+            per_step = _profile_value("stepwise", f"traffic_bytes_per_step_R{R}")
+            sw["roofline"]["traffic"] = per_step * sw_steps if per_step is not None else None
 
     roof = hbm_roofline(sparse_bytes_per_step(g.n, g.nnz, R), steps, kern_ms,
                         "persistent_sparse_kernel",
@@ -421,8 +434,8 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
                            K=K[:st], Ks=Ks[:st], sigma=sg[:st], seeds=synth.seeds(Rs, 0),
                            nthreads=threads)
         out["cpu_baseline"] = oracle_baseline(sample, float(g.nnz),
-                                              {"desc": f"{label}, first steps of the schedule",
-                                               "replicas": R},
+                                              {"desc": f"{label}, the schedule from its start",
+                                               "replicas": R, "max_steps": steps},
                                               target_1t=args.cpu_seconds * 0.4,
                                               target_nt=args.cpu_seconds * 0.6)
     prob.close()
@@ -638,7 +651,8 @@ def colouring_workload(args):
                                   seeds=synth.seeds(Rs, 0), nthreads=threads)
         out["cpu_baseline"] = oracle_baseline(
             sample_fn, float(sb.nnz),
-            {"desc": "the first 64 graphs of the batch as one block-diagonal problem"},
+            {"desc": "the first 64 graphs of the batch as one block-diagonal problem",
+             "max_steps": steps},
             target_1t=args.cpu_seconds * 0.2, target_nt=args.cpu_seconds * 0.3)
     prob.close()
     return out
@@ -712,7 +726,8 @@ def dense_workload(args, n=4096, fp32=False):
             lambda Rs, st, threads: oracle.run_dense(
                 Jd, synth.theta0(Rs, n, seed=100), q=q, dt=DT, K=Kh[:st], Ks=Ksh[:st],
                 sigma=sgh[:st], seeds=synth.seeds(Rs, 0), nthreads=threads),
-            float(n) * (n - 1), {"desc": "the same J and schedule, first steps"},
+            float(n) * (n - 1), {"desc": "the same J and schedule, first steps",
+                                 "max_steps": len(Kh)},
             target_1t=args.cpu_seconds * 0.2, target_nt=args.cpu_seconds * 0.3)
         # the GPU result on a sample against the FP64 oracle
         Rs, st = 4, 50
@@ -827,7 +842,8 @@ def adjoint_workload(args):
                 g.row_ptr, g.col, J1, synth.theta0(Rs, g.n, seed=100), q=q, dt=DT, K=K[:st],
                 Ks=Ks[:st], sigma=sg[:st], seeds=synth.seeds(Rs, 0), nthreads=threads),
             float(g.nnz), {"desc": "forward integration of graph 0 (the oracle's forward "
-                                   "trajectory; its adjoint stores every state)"},
+                                   "trajectory; its adjoint stores every state)",
+                           "max_steps": steps},
             target_1t=args.cpu_seconds * 0.2, target_nt=args.cpu_seconds * 0.3)
     prob.close()
     return out

@@ -61,12 +61,13 @@ def _problem(oim, g, J):
     return oim.Problem.from_csr(g.n, g.row_ptr, g.col, J)
 
 
-def _check_parity(orc, oim, g, J, q, R, steps_total, use, seed_th=7, seed_base=0, step0=0):
+def _check_parity(orc, oim, g, J, q, R, steps_total, use, seed_th=7, seed_base=0, step0=0,
+                  flags=0):
     prob = _problem(oim, g, J)
     K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, steps_total, use)
     th0 = synth.theta0(R, g.n, seed=seed_th)
     sd = synth.seeds(R, seed_base)
-    got, _ = _gpu_run(oim, prob, th0, K, Ks, sg, sd, q, step0=step0)
+    got, _ = _gpu_run(oim, prob, th0, K, Ks, sg, sd, q, step0=step0, flags=flags)
     want = orc.run_csr(g.row_ptr, g.col, J, th0, q=q, dt=DT, K=K, Ks=Ks, sigma=sg, seeds=sd,
                        step0=step0)
     err = wrapdiff(got, want).max()
@@ -99,12 +100,16 @@ def test_generic_q_parity(dev, oim, orc, q):
     _check_parity(orc, oim, g, -g.w, q=q, R=2, steps_total=1000, use=100)
 
 
-def test_isolated_oscillators_and_tiny_n(dev, oim, orc):
-    # n = 1 (no edges): SHIL and noise only; n = 6 with an empty row
+@pytest.mark.parametrize("loop", ["persistent", "stepwise"])
+def test_isolated_oscillators_and_tiny_n(dev, oim, orc, loop):
+    # n = 1 (no edges): SHIL and noise only; n = 6 with empty rows and a
+    # partial last quad; both loop forms
+    flags = oim.OIM_LOOP_STEPWISE if loop == "stepwise" else oim.OIM_LOOP_PERSISTENT
     g = synth.csr_from_edges(1, [], [], [])
-    _check_parity(orc, oim, g, np.zeros(0, np.float32), q=2, R=5, steps_total=300, use=100)
+    _check_parity(orc, oim, g, np.zeros(0, np.float32), q=2, R=5, steps_total=300, use=100,
+                  flags=flags)
     g = synth.csr_from_edges(6, [0, 1, 2], [1, 2, 3], [1.0, -2.0, 0.5])
-    _check_parity(orc, oim, g, -g.w, q=2, R=2, steps_total=300, use=100)
+    _check_parity(orc, oim, g, -g.w, q=2, R=2, steps_total=300, use=100, flags=flags)
 
 
 def test_full_width_sampled_replicas(dev, oim, orc):
