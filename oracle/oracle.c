@@ -449,8 +449,8 @@ double orc_h_eq6(int32_t n, const int64_t* row_ptr, const int32_t* col, const do
 }
 
 /* ------------------------------------------------------------------------ */
-/* Readouts in one fixed FP64 order (the reading this build takes of "cut    */
-/* values bit-exact from identical spins" for real weights; integer weights  */
+/* Readouts in one fixed FP64 order, so that real-weighted cut and energy    */
+/* values from identical spins are reproducible bit for bit (integer weights */
 /* give the same value in any order).  Each row i sums its terms over the    */
 /* upper triangle j > i in ascending column order, starting from +0.  The    */
 /* row sums are then combined by the pairwise tree over rows: the rows are   */
