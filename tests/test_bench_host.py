@@ -46,3 +46,23 @@ def test_one_flip_descent_on_a_tiny_graph_is_at_most_the_maximum_cut():
     for seed in range(5):
         s0 = np.random.default_rng(seed).integers(0, 2, g.n).astype(np.int8)
         assert bench._one_flip_descent(g, s0) <= best
+
+
+def test_oracle_sample_longer_than_the_schedule_reruns_it(monkeypatch):
+    # the rate counts only steps the sampler was asked to run, each call no
+    # longer than the schedule
+    host = bench.host_cpu()
+    host["threads_used"] = 2
+    monkeypatch.setattr(bench, "host_cpu", lambda: host)
+    calls = []
+
+    def run(R, steps, threads):
+        calls.append((R, steps, threads))
+
+    out = bench.oracle_baseline(run, 10.0, {"desc": "x", "replicas": 1, "max_steps": 7},
+                                target_1t=1e-4, target_nt=1e-4)
+    assert calls and max(c[1] for c in calls) <= 7
+    # every timed leg ran exactly the steps it reports
+    s1 = int(out["sample"].split("and 1 replica x ")[1].split(" steps")[0])
+    legs = [c for c in calls if c[2] == 1][1:]  # after the 2-step probe
+    assert sum(c[1] for c in legs) == s1
