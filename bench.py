@@ -44,6 +44,8 @@ MFMA_FP32_PEAK_TFLOPS = 157.3
 DT = float(np.float32(0.01))
 
 SPARSE_SOURCES = ["paper_2505_22631_amd/csrc/sparse_persistent.hip",
+                  "paper_2505_22631_amd/csrc/sparse_persistent_uw.hip",
+                  "paper_2505_22631_amd/csrc/persistent_kernel.hpp",
                   "paper_2505_22631_amd/csrc/noise.hpp", "paper_2505_22631_amd/csrc/phase.hpp",
                   "paper_2505_22631_amd/csrc/tree.hpp"]
 DENSE_SOURCES = ["paper_2505_22631_amd/csrc/dense.hip", "paper_2505_22631_amd/csrc/noise.hpp",

@@ -123,6 +123,10 @@ typedef struct {
     double max_abs_row_sum;    /* max_i sum_j |J_ij| (Gershgorin bound of J)         */
     double sum_J_upper;        /* sum_{i<j} J_ij; max-cut total weight W = -this     */
     int32_t max_instance_n;    /* oscillators of the largest instance (n if one)    */
+    float uniform_weight;      /* +1 or -1 when every stored J equals it (the      */
+                               /* LDS-resident loop then reads a half-size image   */
+                               /* of neighbour offsets alone, same results bit for */
+                               /* bit), else 0                                     */
 } oim_problem_info;
 
 /* Fills *info (host memory).  Synchronous, no device work. */

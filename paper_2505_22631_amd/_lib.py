@@ -46,7 +46,8 @@ class TuneReport(ctypes.Structure):
 class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", _i32), ("is_dense", _i32), ("nnz", _i64), ("integer_weights", _i32),
                 ("n_instances", _i32), ("max_abs_row_sum", ctypes.c_double),
-                ("sum_J_upper", ctypes.c_double), ("max_instance_n", _i32)]
+                ("sum_J_upper", ctypes.c_double), ("max_instance_n", _i32),
+                ("uniform_weight", _f32)]
 
 
 # every symbol declared in include/oim.h, with its ctypes prototype

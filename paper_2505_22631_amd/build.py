@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "liboim.so")
 OBJ = os.path.join(HERE, "_build")
-SOURCES = ["api.cpp", "validate.cpp", "readout.hip", "sparse_persistent.hip", "stepwise.hip",
+SOURCES = ["api.cpp", "validate.cpp", "readout.hip", "sparse_persistent.hip",
+           "sparse_persistent_uw.hip", "stepwise.hip",
            "dense.hip", "adjoint.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

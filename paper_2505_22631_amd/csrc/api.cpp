@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -43,6 +44,7 @@ void release(Problem* p) {
     hipFree(p->d_J);
     hipFree(p->d_sell_desc);
     hipFree(p->d_sell);
+    hipFree(p->d_sell_uw);
     hipFree(p->d_inst);
     hipFree(p->d_order);
     stepwise_release(p);
@@ -154,7 +156,16 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
     }
     weight_stats(p, n, row_ptr, col_idx, J);
     SellImage img;
-    build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img);
+    // one weight of +1 or -1 on every entry: the kernel reads a half-size
+    // image of offsets alone (OIM_UNIFORM_WEIGHT_IMAGE=0 keeps the general one)
+    float w0 = nnz > 0 ? J[0] : 0.f;
+    if (!(w0 == 1.0f || w0 == -1.0f)) w0 = 0.f;
+    for (int64_t e = 1; e < nnz && w0 != 0.f; ++e)
+        if (J[e] != w0) w0 = 0.f;
+    if (const char* env = getenv("OIM_UNIFORM_WEIGHT_IMAGE"))
+        if (atoi(env) == 0) w0 = 0.f;
+    build_sell(n, row_ptr, col_idx, J, n_inst, n_inst > 1 ? inst_off : nullptr, img, w0);
+    p->uniform_w = w0;
     p->sell_slices = img.slices;
     p->max_slices = img.max_slices;
     p->sell_entries = (int64_t)img.entries.size();
@@ -168,6 +179,8 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
         (st = dev_upload(&p->d_J, J, (size_t)nnz, "upload J", kCsrPad)) ||
         (st = dev_upload(&p->d_sell_desc, img.desc.data(), img.desc.size(), "upload slices")) ||
         (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell")) ||
+        (st = dev_upload(&p->d_sell_uw, img.entries_uw.data(), img.entries_uw.size(),
+                         "upload unit-weight sell")) ||
         (st = dev_upload(&p->d_inst, img.inst.data(), img.inst.size(), "upload instances")) ||
         (st = dev_upload(&p->d_order, img.order.data(), img.order.size(), "upload order"))) {
         release(p);
@@ -246,6 +259,7 @@ __attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
     info->max_abs_row_sum = p->max_abs_row_sum;
     info->sum_J_upper = p->sum_J_upper;
     info->max_instance_n = p->dense ? p->n : p->max_inst_n;
+    info->uniform_weight = p->d_sell_uw ? p->uniform_w : 0.f;
     return OIM_OK;
 }
 

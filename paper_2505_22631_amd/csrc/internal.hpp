@@ -31,6 +31,13 @@ struct SellImage {
     int32_t slices = 0;
     std::vector<int2> desc;      // [slices]: (base_s in int4 rows, deg_s)
     std::vector<int2> entries;   // [sum_s 4 * deg_s * 64]
+    // With one weight w0 = +-1 on every entry, the same rows as LDS byte
+    // offsets alone, four consecutive entries of a row per 16 bytes:
+    //   uint4 index = (base_s / 2 + j * deg_s / 4 + e / 4) * 64 + l, word e % 4;
+    // padding entries point at the zero entry after the table and the
+    // readout colours (byte offset 36 * 64 * slices of the instance).  Empty
+    // otherwise.
+    std::vector<uint32_t> entries_uw;
     std::vector<int4> inst;      // [instances]: (first slice, slices, first oscillator, n_b)
     std::vector<int32_t> order;  // instances, most slices first
     int32_t max_slices = 0;
@@ -73,6 +80,8 @@ struct Problem {
     int64_t sell_entries = 0;
     int2* d_sell_desc = nullptr;
     int2* d_sell = nullptr;
+    uint32_t* d_sell_uw = nullptr;  // unit-weight image, or null
+    float uniform_w = 0.f;          // the weight every entry shares (+1 or -1), or 0
 
     // device: dense coupling (dense problems), FP32 and the BF16 split
     float* d_Jdense = nullptr;
@@ -118,8 +127,10 @@ Problem* checked(oim_problem h);
 void unregister_problem(Problem* p);
 int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, int32_t n_inst,
                     const int32_t* inst_off);
+// uniform_w: the weight every entry shares (+1 or -1) to build the
+// unit-weight image too, or 0.
 void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
-                int32_t n_inst, const int32_t* inst_off, SellImage& out);
+                int32_t n_inst, const int32_t* inst_off, SellImage& out, float uniform_w = 0.f);
 
 // kernels' host launchers
 int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,

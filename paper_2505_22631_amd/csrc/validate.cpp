@@ -179,9 +179,11 @@ int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, i
 }
 
 void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
-                int32_t n_inst, const int32_t* inst_off, SellImage& out) {
+                int32_t n_inst, const int32_t* inst_off, SellImage& out, float uniform_w) {
     out.desc.clear();
     out.entries.clear();
+    out.entries_uw.clear();
+    const bool uw = uniform_w == 1.0f || uniform_w == -1.0f;
     out.inst.clear();
     out.max_slices = 0;
     int64_t rows4 = 0;  // running offset in int4 rows (64 int4 per row)
@@ -205,6 +207,9 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
             out.desc.push_back(int2{(int32_t)rows4, deg});
             const size_t first = out.entries.size();
             out.entries.resize(first + (size_t)4 * deg / 2 * kSliceQuads * 2, int2{0, 0});
+            const size_t first_uw = out.entries_uw.size();
+            if (uw) out.entries_uw.resize(first_uw + (size_t)4 * deg * kSliceQuads, 0u);
+            const uint32_t zero_off = (uint32_t)(36 * plane);  // after table and colours
             for (int j = 0; j < 4; ++j) {
                 for (int l = 0; l < kSliceQuads; ++l) {
                     const int64_t i = 4LL * (s * kSliceQuads + l) + j;  // local index
@@ -223,6 +228,11 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
                         }
                         const int64_t q4 = ((int64_t)j * (deg / 2) + e / 2) * kSliceQuads + l;
                         out.entries[first + (size_t)(q4 * 2 + (e & 1))] = v;
+                        if (uw) {
+                            const int64_t u4 = ((int64_t)j * (deg / 4) + e / 4) * kSliceQuads + l;
+                            out.entries_uw[first_uw + (size_t)(u4 * 4 + (e & 3))] =
+                                e < rl ? (uint32_t)v.x : zero_off;
+                        }
                     }
                 }
             }

@@ -87,6 +87,25 @@ int main() {
             check(bimg.inst.size() == 2 && bimg.order.size() == 2, "batch image");
         }
     }
+    // the unit-weight image: same rows, offsets alone, padding at the zero
+    // entry after the table and colours
+    for (int32_t n : {5, 300, 900}) {
+        Csr g = random_graph(n, 21u + n, 30);
+        for (float& w : g.J) w = -1.f;
+        SellImage img;
+        build_sell(g.n, g.rp.data(), g.col.data(), g.J.data(), 1, nullptr, img, -1.f);
+        check(img.entries_uw.size() == img.entries.size(), "unit-weight image size");
+        const uint32_t zoff = (uint32_t)(36 * 64 * img.slices);
+        size_t real = 0;
+        for (uint32_t o : img.entries_uw) {
+            check(o == zoff || o < (uint32_t)(32 * 64 * img.slices), "offset in the table or zero");
+            real += o != zoff;
+        }
+        check(real == g.col.size(), "every stored entry once");
+        SellImage plain;
+        build_sell(g.n, g.rp.data(), g.col.data(), g.J.data(), 1, nullptr, plain, 0.f);
+        check(plain.entries_uw.empty(), "no unit-weight image without a uniform weight");
+    }
     // malformed inputs are rejected, never read out of bounds
     Csr g = random_graph(40, 11u, 150);
     {

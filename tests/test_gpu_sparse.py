@@ -205,6 +205,44 @@ def test_block_size_variants_agree(dev, oim, orc):
     np.testing.assert_array_equal(outs[0], outs[2])
 
 
+@pytest.mark.parametrize("case", ["maxcut_unit", "ferro", "colouring_batch"])
+def test_unit_weight_image_is_bit_identical(dev, oim, case, monkeypatch):
+    # couplings that all share one weight, -1 or +1, run on the half-size
+    # image of neighbour offsets; phases, phase words and every in-run
+    # readout equal the general image's bit for bit
+    import torch
+    if case == "maxcut_unit":
+        g, w, q, R, off = c1_graph(), -1.0, 2, 3, None
+    elif case == "ferro":
+        g, w, q, R, off = synth.torus(20, 30, seed=2), 1.0, 2, 4, None
+    else:
+        g, off, _ = _batch(24, 11)
+        w, q, R = -1.0, 3, 2
+    J = np.full(g.nnz, w, np.float32)
+    outs = []
+    for general in (False, True):
+        if general:
+            monkeypatch.setenv("OIM_UNIFORM_WEIGHT_IMAGE", "0")
+        else:
+            monkeypatch.delenv("OIM_UNIFORM_WEIGHT_IMAGE", raising=False)
+        prob = (oim.Problem.from_csr(g.n, g.row_ptr, g.col, J) if off is None else
+                oim.Problem.from_csr_blocks(g.n, g.row_ptr, g.col, J, off))
+        assert prob.info["uniform_weight"] == (0.0 if general else w)
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, 600, 300)
+        th0 = synth.theta0(R, g.n, seed=3)
+        th, ro, words = _gpu_run(oim, prob, th0, K, Ks, sg, synth.seeds(R, 5), q,
+                                 readout_every=25, want_best=True,
+                                 phase=_phase_words(th0))
+        outs.append((th, ro, words))
+        prob.close()
+    (th_u, ro_u, w_u), (th_g, ro_g, w_g) = outs
+    np.testing.assert_array_equal(w_u, w_g)
+    np.testing.assert_array_equal(th_u, th_g)
+    for name in ("trace", "best_h", "best_step", "best_colour"):
+        np.testing.assert_array_equal(ro_u[name], ro_g[name], err_msg=name)
+    print(f"{case}: unit-weight image bit-identical ({R} replicas)", flush=True)
+
+
 def test_steps_zero_leaves_theta(dev, oim):
     g = synth.cycle(10)
     prob = _problem(oim, g, -g.w)

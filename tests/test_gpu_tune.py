@@ -63,18 +63,20 @@ def test_every_variant_gives_identical_bits(oim):
 
 
 @pytest.mark.parametrize("q", [2, 3, 5])
-def test_split_row_variants_give_identical_bits(oim, q):
+@pytest.mark.parametrize("signed", [True, False])
+def test_split_row_variants_give_identical_bits(oim, q, signed):
     # few slices and long rows (the G(800, 0.06) shape, degree ~48, and a
     # ragged tail): every launch variant, whole-quad and split-row, gives the
-    # same phases and the same in-run readouts (trace, best, colours)
+    # same phases and the same in-run readouts (trace, best, colours); with
+    # every weight -1 (signed=False) the variants read the unit-weight image
     import torch
     g = synth.erdos_renyi(800, 0.06, seed=0)
-    J = (-g.w).astype(np.float32)
-    g2 = synth.gnp_avg_degree(301, 30.0, seed=4, signed=True)
+    g2 = synth.gnp_avg_degree(301, 30.0, seed=4, signed=signed)
     big, off = synth.block_diagonal([g, g2])
     Jb = (-big.w).astype(np.float32)
     R, steps = 3, 90
     with oim.Problem.from_csr_blocks(big.n, big.row_ptr, big.col, Jb, off) as prob:
+        assert prob.info["uniform_weight"] == (0.0 if signed else -1.0)
         kmax = 4 * 0.5 / (DT * prob.info["max_abs_row_sum"])
         K = torch.from_numpy(synth.ramp(0.0, kmax, steps)).cuda()
         Ks = torch.from_numpy(synth.ramp(0.0, 0.5 / (DT * q), steps)).cuda()
@@ -100,7 +102,7 @@ def test_split_row_variants_give_identical_bits(oim, q):
         np.testing.assert_array_equal(th, ref_th, err_msg=f"variant {k}")
         for name in ("trace", "best_h", "best_step", "best_colour"):
             np.testing.assert_array_equal(ro[name], ref_ro[name], err_msg=f"variant {k} {name}")
-    print(f"q={q}: {len(outs)} variants identical", flush=True)
+    print(f"q={q} signed={signed}: {len(outs)} variants identical", flush=True)
 
 
 def test_autotune_keeps_a_variant_and_leaves_theta(oim):
