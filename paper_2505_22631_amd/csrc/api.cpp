@@ -45,6 +45,7 @@ void release(Problem* p) {
     hipFree(p->d_sell_desc);
     hipFree(p->d_sell);
     hipFree(p->d_sell_uw);
+    hipFree(p->d_row_split);
     hipFree(p->d_inst);
     hipFree(p->d_order);
     stepwise_release(p);
@@ -181,6 +182,8 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
         (st = dev_upload(&p->d_sell, img.entries.data(), img.entries.size(), "upload sell")) ||
         (st = dev_upload(&p->d_sell_uw, img.entries_uw.data(), img.entries_uw.size(),
                          "upload unit-weight sell")) ||
+        (st = dev_upload(&p->d_row_split, img.row_split.data(), img.row_split.size(),
+                         "upload row split")) ||
         (st = dev_upload(&p->d_inst, img.inst.data(), img.inst.size(), "upload instances")) ||
         (st = dev_upload(&p->d_order, img.order.data(), img.order.size(), "upload order"))) {
         release(p);

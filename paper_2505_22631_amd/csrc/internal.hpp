@@ -38,6 +38,11 @@ struct SellImage {
     // readout colours (byte offset 36 * 64 * slices of the instance).  Empty
     // otherwise.
     std::vector<uint32_t> entries_uw;
+    // Per slice s (of the whole batch), row j, lane l, at (s * 4 + j) * 64 + l:
+    // (index of the row's first entry with column > the row's own index,
+    // row length); rows past an instance's end are (0, 0).  The readouts sum
+    // a row's entries from the first to the second.
+    std::vector<int2> row_split;
     std::vector<int4> inst;      // [instances]: (first slice, slices, first oscillator, n_b)
     std::vector<int32_t> order;  // instances, most slices first
     int32_t max_slices = 0;
@@ -81,6 +86,7 @@ struct Problem {
     int2* d_sell_desc = nullptr;
     int2* d_sell = nullptr;
     uint32_t* d_sell_uw = nullptr;  // unit-weight image, or null
+    int2* d_row_split = nullptr;    // SellImage::row_split
     float uniform_w = 0.f;          // the weight every entry shares (+1 or -1), or 0
 
     // device: dense coupling (dense problems), FP32 and the BF16 split

@@ -45,6 +45,7 @@ namespace persist {
 struct PersistArgs {
     const int4* sell;   // sliced-ELL entries, two per int4 (see SellImage)
     const int4* sell_uw;  // uniform unit weights: LDS offsets alone, four per int4, or null
+    const int2* row_split;  // per slice, row j, lane: (first entry of the upper triangle, length)
     uint32_t sell_uw_bytes;
     float w0;           // the uniform weight (+1 or -1) when sell_uw is set
     const int2* desc;   // per slice: (base in int4 rows, padded degree)
@@ -417,8 +418,9 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
             }
             __syncthreads();
             // Eq. 1 / Eq. 2 in the library's fixed FP64 order: each row sums
-            // its terms over j > i in column order (the ELL row is the CSR row,
-            // its padding adds zeros); a quad's rows fold as (r0 + r1) +
+            // its terms over j > i in column order (the ELL row is the CSR row;
+            // its entries from the row's split point to its length are the
+            // upper triangle); a quad's rows fold as (r0 + r1) +
             // (r2 + r3) and the lanes by the xor butterfly (partner distance
             // 1, 2, ..., 32), which is the pairwise tree over the slice's 256
             // rows.  The tree over slices: with room in LDS every slice's sum
@@ -442,77 +444,167 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                     const int m = slice * 64 + lane;
                     double rs[RPL];
                     int ci[RPL];
+                    // Whole quads (the common shapes) find a neighbour's index from
+                    // its LDS slot; split-row shapes, whose rows are long, read each
+                    // row's split point instead (fewer operations per entry, more
+                    // registers, which the whole-quad shapes cannot spare).
+                    if constexpr (RPL == 4) {
 #pragma unroll
-                    for (int jj = 0; jj < RPL; ++jj) {
-                        rs[jj] = 0.0;
-                        ci[jj] = col8[(j0 + jj) * plane + m];
-                    }
-                    if constexpr (UWT) {
-                        // the unit-weight image: four offsets per load, the
-                        // padding (the zero entry's offset) skipped; the terms
-                        // are those of the general image in the same order
-                        const int D4 = D2 >> 1;
-                        const int zoff = 36 * plane;
-                        const float wu = a.w0;
-                        constexpr int UR4 = RPL == 1 ? 2 : 1;
-                        for (int e4 = 0; e4 < D4; e4 += UR4) {
-                            int4 e[RPL][UR4];
+                        for (int jj = 0; jj < RPL; ++jj) {
+                            rs[jj] = 0.0;
+                            ci[jj] = col8[(j0 + jj) * plane + m];
+                        }
+                        if constexpr (UWT) {
+                            // the unit-weight image: four offsets per load, the
+                            // padding (the zero entry's offset) skipped; the terms
+                            // are those of the general image in the same order
+                            const int D4 = D2 >> 1;
+                            const int zoff = 36 * plane;
+                            const float wu = a.w0;
+                            constexpr int UR4 = RPL == 1 ? 2 : 1;
+                            for (int e4 = 0; e4 < D4; e4 += UR4) {
+                                int4 e[RPL][UR4];
 #pragma unroll
-                            for (int jj = 0; jj < RPL; ++jj)
+                                for (int jj = 0; jj < RPL; ++jj)
 #pragma unroll
-                                for (int h = 0; h < UR4; ++h)
-                                    if (h == 0 || e4 + h < D4)
-                                        e[jj][h] = load_pair(rsrc_uw, voff + h * 1024,
-                                                             ((sb >> 1) + (j0 + jj) * D4 + e4) * 1024);
+                                    for (int h = 0; h < UR4; ++h)
+                                        if (h == 0 || e4 + h < D4)
+                                            e[jj][h] = load_pair(rsrc_uw, voff + h * 1024,
+                                                                 ((sb >> 1) + (j0 + jj) * D4 + e4) * 1024);
 #pragma unroll
-                            for (int jj = 0; jj < RPL; ++jj) {
-                                const int own = 4 * m + j0 + jj;
+                                for (int jj = 0; jj < RPL; ++jj) {
+                                    const int own = 4 * m + j0 + jj;
 #pragma unroll
-                                for (int h = 0; h < UR4; ++h) {
-                                    if (h >= 1 && e4 + h >= D4) break;
-                                    const int o4[4] = {e[jj][h].x, e[jj][h].y, e[jj][h].z, e[jj][h].w};
+                                    for (int h = 0; h < UR4; ++h) {
+                                        if (h >= 1 && e4 + h >= D4) break;
+                                        const int o4[4] = {e[jj][h].x, e[jj][h].y, e[jj][h].z, e[jj][h].w};
 #pragma unroll
-                                    for (int x = 0; x < 4; ++x) {
-                                        if (o4[x] == zoff) continue;
-                                        const int c = col8[o4[x] >> 3];
-                                        const bool up = slot_index(o4[x] >> 3, plane) > own;
-                                        const float tt = (q == 2) ? (ci[jj] == c ? wu : -wu)
-                                                                  : (ci[jj] == c ? wu : 0.f);
-                                        rs[jj] += up ? (double)tt : 0.0;
+                                        for (int x = 0; x < 4; ++x) {
+                                            if (o4[x] == zoff) continue;
+                                            const int c = col8[o4[x] >> 3];
+                                            const bool up = slot_index(o4[x] >> 3, plane) > own;
+                                            const float tt = (q == 2) ? (ci[jj] == c ? wu : -wu)
+                                                                      : (ci[jj] == c ? wu : 0.f);
+                                            rs[jj] += up ? (double)tt : 0.0;
+                                        }
+                                    }
+                                }
+                            }
+                        } else {
+                            // UR entry pairs of every row per iteration (8 loads in
+                            // all for whole quads, 4 for split rows, which have fewer
+                            // registers to spare), issued before the first is used;
+                            // each row still adds its terms in entry order
+                            constexpr int UR = RPL == 4 ? 2 : 4 / RPL;
+                            for (int e2 = 0; e2 < D2; e2 += UR) {
+                                int4 e[RPL][UR];
+#pragma unroll
+                                for (int jj = 0; jj < RPL; ++jj)
+#pragma unroll
+                                    for (int h = 0; h < UR; ++h)
+                                        if (h < 2 || e2 + h < D2)
+                                            e[jj][h] = load_pair(rsrc, voff + h * 1024, (sb + (j0 + jj) * D2 + e2) * 1024);
+#pragma unroll
+                                for (int jj = 0; jj < RPL; ++jj) {
+                                    const int own = 4 * m + j0 + jj;
+#pragma unroll
+                                    for (int h = 0; h < UR; ++h) {
+                                        if (h >= 2 && e2 + h >= D2) break;
+                                        const int4 x = e[jj][h];
+                                        const int c0 = col8[x.x >> 3], c1 = col8[x.z >> 3];
+                                        const float w0 = __int_as_float(x.y), w1 = __int_as_float(x.w);
+                                        // upper triangle only: the neighbour's index from its slot
+                                        const bool up0 = slot_index(x.x >> 3, plane) > own;
+                                        const bool up1 = slot_index(x.z >> 3, plane) > own;
+                                        const float t0 = (q == 2) ? (ci[jj] == c0 ? w0 : -w0) : (ci[jj] == c0 ? w0 : 0.f);
+                                        const float t1 = (q == 2) ? (ci[jj] == c1 ? w1 : -w1) : (ci[jj] == c1 ? w1 : 0.f);
+                                        rs[jj] += up0 ? (double)t0 : 0.0;
+                                        rs[jj] += up1 ? (double)t1 : 0.0;
                                     }
                                 }
                             }
                         }
                     } else {
-                        // UR entry pairs of every row per iteration (8 loads in
-                        // all for whole quads, 4 for split rows, which have fewer
-                        // registers to spare), issued before the first is used;
-                        // each row still adds its terms in entry order
-                        constexpr int UR = RPL == 4 ? 2 : 4 / RPL;
-                        for (int e2 = 0; e2 < D2; e2 += UR) {
-                            int4 e[RPL][UR];
+                        // the row's upper triangle j > i: its entries from p on
+                        // (columns ascend along a row), before its length
+                        int up0[RPL], rlen[RPL];
 #pragma unroll
-                            for (int jj = 0; jj < RPL; ++jj)
+                        for (int jj = 0; jj < RPL; ++jj) {
+                            rs[jj] = 0.0;
+                            ci[jj] = col8[(j0 + jj) * plane + m];
+                            const int2 sp = a.row_split[((slice0 + slice) * 4 + j0 + jj) * 64 + lane];
+                            up0[jj] = sp.x;
+                            rlen[jj] = sp.y;
+                        }
+                        if constexpr (UWT) {
+                            // the unit-weight image: four offsets per load; every
+                            // term is +-w0 (or 0), so the row counts them in an
+                            // integer, whose product with w0 is the sum of the
+                            // terms in any order, exactly
+                            const int D4 = D2 >> 1;
+                            constexpr int UR4 = RPL == 1 ? 2 : 1;
+                            int cnt[RPL];
 #pragma unroll
-                                for (int h = 0; h < UR; ++h)
-                                    if (h < 2 || e2 + h < D2)
-                                        e[jj][h] = load_pair(rsrc, voff + h * 1024, (sb + (j0 + jj) * D2 + e2) * 1024);
+                            for (int jj = 0; jj < RPL; ++jj) cnt[jj] = 0;
+                            for (int e4 = 0; e4 < D4; e4 += UR4) {
+                                int4 e[RPL][UR4];
 #pragma unroll
-                            for (int jj = 0; jj < RPL; ++jj) {
-                                const int own = 4 * m + j0 + jj;
+                                for (int jj = 0; jj < RPL; ++jj)
 #pragma unroll
-                                for (int h = 0; h < UR; ++h) {
-                                    if (h >= 2 && e2 + h >= D2) break;
-                                    const int4 x = e[jj][h];
-                                    const int c0 = col8[x.x >> 3], c1 = col8[x.z >> 3];
-                                    const float w0 = __int_as_float(x.y), w1 = __int_as_float(x.w);
-                                    // upper triangle only: the neighbour's index from its slot
-                                    const bool up0 = slot_index(x.x >> 3, plane) > own;
-                                    const bool up1 = slot_index(x.z >> 3, plane) > own;
-                                    const float t0 = (q == 2) ? (ci[jj] == c0 ? w0 : -w0) : (ci[jj] == c0 ? w0 : 0.f);
-                                    const float t1 = (q == 2) ? (ci[jj] == c1 ? w1 : -w1) : (ci[jj] == c1 ? w1 : 0.f);
-                                    rs[jj] += up0 ? (double)t0 : 0.0;
-                                    rs[jj] += up1 ? (double)t1 : 0.0;
+                                    for (int h = 0; h < UR4; ++h)
+                                        if (h == 0 || e4 + h < D4)
+                                            e[jj][h] = load_pair(rsrc_uw, voff + h * 1024,
+                                                                 ((sb >> 1) + (j0 + jj) * D4 + e4) * 1024);
+#pragma unroll
+                                for (int jj = 0; jj < RPL; ++jj) {
+#pragma unroll
+                                    for (int h = 0; h < UR4; ++h) {
+                                        if (h >= 1 && e4 + h >= D4) break;
+                                        const int o4[4] = {e[jj][h].x, e[jj][h].y, e[jj][h].z, e[jj][h].w};
+#pragma unroll
+                                        for (int x = 0; x < 4; ++x) {
+                                            const int idx = 4 * (e4 + h) + x;
+                                            const bool up = idx >= up0[jj] && idx < rlen[jj];
+                                            // (padding, never counted, points past the colours)
+                                            const bool eq = ci[jj] == col8[up ? o4[x] >> 3 : 0];
+                                            const int tt = eq ? 1 : (q == 2 ? -1 : 0);
+                                            cnt[jj] += up ? tt : 0;
+                                        }
+                                    }
+                                }
+                            }
+#pragma unroll
+                            for (int jj = 0; jj < RPL; ++jj) rs[jj] = (double)a.w0 * (double)cnt[jj];
+                        } else {
+                            // UR entry pairs of every row per iteration (8 loads in
+                            // all for whole quads, 4 for split rows, which have fewer
+                            // registers to spare), issued before the first is used;
+                            // each row adds its terms in entry order
+                            constexpr int UR = RPL == 4 ? 2 : 4 / RPL;
+                            for (int e2 = 0; e2 < D2; e2 += UR) {
+                                int4 e[RPL][UR];
+#pragma unroll
+                                for (int jj = 0; jj < RPL; ++jj)
+#pragma unroll
+                                    for (int h = 0; h < UR; ++h)
+                                        if (h < 2 || e2 + h < D2)
+                                            e[jj][h] = load_pair(rsrc, voff + h * 1024, (sb + (j0 + jj) * D2 + e2) * 1024);
+#pragma unroll
+                                for (int jj = 0; jj < RPL; ++jj) {
+#pragma unroll
+                                    for (int h = 0; h < UR; ++h) {
+                                        if (h >= 2 && e2 + h >= D2) break;
+                                        const int4 x = e[jj][h];
+                                        const int i0 = 2 * (e2 + h);
+                                        const bool u0 = i0 >= up0[jj] && i0 < rlen[jj];
+                                        const bool u1 = i0 + 1 >= up0[jj] && i0 + 1 < rlen[jj];
+                                        const int c0 = col8[x.x >> 3], c1 = col8[x.z >> 3];
+                                        const float w0 = __int_as_float(x.y), w1 = __int_as_float(x.w);
+                                        const float t0 = (q == 2) ? (ci[jj] == c0 ? w0 : -w0) : (ci[jj] == c0 ? w0 : 0.f);
+                                        const float t1 = (q == 2) ? (ci[jj] == c1 ? w1 : -w1) : (ci[jj] == c1 ? w1 : 0.f);
+                                        rs[jj] += u0 ? (double)t0 : 0.0;
+                                        rs[jj] += u1 ? (double)t1 : 0.0;
+                                    }
                                 }
                             }
                         }

@@ -118,6 +118,7 @@ int launch_variant(const Problem* p, const oim_run_cfg* cfg, const float* K, con
         return set_error(OIM_E_UNSUPPORTED, "replica does not fit the LDS-resident kernel");
     PersistArgs a{};
     a.sell = reinterpret_cast<const int4*>(p->d_sell);
+    a.row_split = p->d_row_split;
     a.desc = p->d_sell_desc;
     a.sell_bytes = (uint32_t)(p->sell_entries * 8);
     a.inst = p->d_inst;

@@ -183,6 +183,7 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
     out.desc.clear();
     out.entries.clear();
     out.entries_uw.clear();
+    out.row_split.clear();
     const bool uw = uniform_w == 1.0f || uniform_w == -1.0f;
     out.inst.clear();
     out.max_slices = 0;
@@ -216,6 +217,9 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
                     const int32_t self = (int32_t)std::min<int64_t>(i, nb - 1);
                     const int64_t rb = i < nb ? row_ptr[o + i] : 0;
                     const int64_t rl = i < nb ? row_ptr[o + i + 1] - row_ptr[o + i] : 0;
+                    int32_t first_up = 0;  // columns ascend along a row
+                    while (first_up < rl && col_idx[rb + first_up] - o <= i) ++first_up;
+                    out.row_split.push_back(int2{first_up, (int32_t)rl});
                     for (int32_t e = 0; e < deg; ++e) {
                         int2 v;
                         if (e < rl) {

@@ -105,6 +105,21 @@ int main() {
         SellImage plain;
         build_sell(g.n, g.rp.data(), g.col.data(), g.J.data(), 1, nullptr, plain, 0.f);
         check(plain.entries_uw.empty(), "no unit-weight image without a uniform weight");
+        // row splits: (first entry with column > the row, row length)
+        check(img.row_split.size() == (size_t)img.slices * 256, "row split size");
+        for (int s = 0; s < img.slices; ++s)
+            for (int j = 0; j < 4; ++j)
+                for (int l = 0; l < 64; ++l) {
+                    const int i = 4 * (s * 64 + l) + j;
+                    const int2 sp = img.row_split[(s * 4 + j) * 64 + l];
+                    if (i >= n) {
+                        check(sp.x == 0 && sp.y == 0, "padding row split");
+                        continue;
+                    }
+                    check(sp.y == (int)(g.rp[i + 1] - g.rp[i]) && sp.x <= sp.y, "row split length");
+                    for (int k = 0; k < sp.y; ++k)
+                        check((g.col[g.rp[i] + k] > i) == (k >= sp.x), "row split point");
+                }
     }
     // malformed inputs are rejected, never read out of bounds
     Csr g = random_graph(40, 11u, 150);
