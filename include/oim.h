@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define OIM_ABI_VERSION 2
+#define OIM_ABI_VERSION 3
 
 typedef enum {
     OIM_OK = 0,

@@ -19,6 +19,10 @@ _P = ctypes.c_void_p
 _i32, _i64, _u32, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes.c_float
 
 
+# OIM_ABI_VERSION of the header these declarations follow
+ABI_VERSION = 3
+
+
 class RunCfg(ctypes.Structure):
     _fields_ = [("q", _i32), ("R", _i32), ("steps", _i32), ("dt", _f32),
                 ("readout_every", _i32), ("flags", _u32)]
@@ -106,6 +110,9 @@ def lib():
             fn = getattr(L, name)
             fn.restype = res
             fn.argtypes = args
+        if L.oim_abi_version() != ABI_VERSION:
+            raise ImportError(f"{LIB_PATH} has ABI version {L.oim_abi_version()}, this binding "
+                              f"{ABI_VERSION}: rebuild the HIP library")
         _lib = L
     return _lib
 

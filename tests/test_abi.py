@@ -35,9 +35,37 @@ def test_every_declared_symbol_is_exported(oim):
     assert set(syms) == set(_lib.PROTOTYPES), "binding prototypes and header disagree"
 
 
+def _header_structs():
+    """{typedef name: [field names in order]} of the header's structs."""
+    text = open(os.path.join(ROOT, "include", "oim.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    out = {}
+    for body, name in re.findall(r"typedef struct\s*\{(.*?)\}\s*(\w+)\s*;", text, flags=re.S):
+        fields = []
+        for decl in body.split(";"):
+            m = re.search(r"(\w+)\s*(\[[^\]]*\])?\s*$", decl.strip())
+            if m and decl.strip():
+                fields.append(m.group(1))
+        out[name] = fields
+    return out
+
+
+def test_binding_structs_match_the_header(oim):
+    # every struct the binding passes through the C ABI has the header's
+    # fields in the header's order
+    from paper_2505_22631_amd import _lib
+    structs = _header_structs()
+    pairs = {"oim_run_cfg": _lib.RunCfg, "oim_readout": _lib.Readout,
+             "oim_adjoint_cfg": _lib.AdjointCfg, "oim_tune_report": _lib.TuneReport,
+             "oim_problem_info": _lib.ProblemInfo}
+    for cname, cls in pairs.items():
+        assert cname in structs, cname
+        assert [f for f, _ in cls._fields_] == structs[cname], cname
+
+
 def test_abi_version_and_status_names(oim):
     from paper_2505_22631_amd import _lib
-    assert oim.oim_abi_version() == 2
+    assert oim.oim_abi_version() == _lib.ABI_VERSION == 3
     assert _lib.status_name(0) == "OIM_OK"
     assert _lib.status_name(3) == "OIM_E_ASYM"
     assert _lib.status_name(99) == "OIM_E_UNKNOWN"
