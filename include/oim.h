@@ -53,7 +53,7 @@
 extern "C" {
 #endif
 
-#define OIM_ABI_VERSION 3
+#define OIM_ABI_VERSION 4
 
 typedef enum {
     OIM_OK = 0,
@@ -127,6 +127,10 @@ typedef struct {
                                /* LDS-resident loop then reads a half-size image   */
                                /* of neighbour offsets alone, same results bit for */
                                /* bit), else 0                                     */
+    int32_t stepwise_row_length; /* entries per row of the padded row image the   */
+                               /* stepwise loop reads (a single graph whose rows   */
+                               /* are of similar length; same results bit for bit  */
+                               /* as the CSR), else 0 (the CSR)                    */
 } oim_problem_info;
 
 /* Fills *info (host memory).  Synchronous, no device work. */

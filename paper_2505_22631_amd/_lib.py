@@ -20,7 +20,7 @@ _i32, _i64, _u32, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32, ctypes
 
 
 # OIM_ABI_VERSION of the header these declarations follow
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 
 class RunCfg(ctypes.Structure):
@@ -51,7 +51,7 @@ class ProblemInfo(ctypes.Structure):
     _fields_ = [("n", _i32), ("is_dense", _i32), ("nnz", _i64), ("integer_weights", _i32),
                 ("n_instances", _i32), ("max_abs_row_sum", ctypes.c_double),
                 ("sum_J_upper", ctypes.c_double), ("max_instance_n", _i32),
-                ("uniform_weight", _f32)]
+                ("uniform_weight", _f32), ("stepwise_row_length", _i32)]
 
 
 # every symbol declared in include/oim.h, with its ctypes prototype

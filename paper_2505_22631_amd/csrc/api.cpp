@@ -42,6 +42,8 @@ void release(Problem* p) {
     hipFree(p->d_row_ptr);
     hipFree(p->d_col);
     hipFree(p->d_J);
+    hipFree(p->d_ell_col);
+    hipFree(p->d_ell_J);
     hipFree(p->d_sell_desc);
     hipFree(p->d_sell);
     hipFree(p->d_sell_uw);
@@ -189,6 +191,20 @@ __attribute__((visibility("default"))) int oim_problem_from_csr_blocks(
         release(p);
         return st;
     }
+    // the padded row image of the stepwise loop (OIM_STEPWISE_ELL=0 never
+    // builds it, =1 builds it for any single graph)
+    int ell_mode = 2;
+    if (const char* env = getenv("OIM_STEPWISE_ELL")) ell_mode = atoi(env) == 0 ? 0 : 1;
+    if (n_inst == 1 && ell_wanted(n, row_ptr, ell_mode)) {
+        EllImage ell;
+        build_ell(n, row_ptr, col_idx, J, ell);
+        p->ell_D = ell.D;
+        if ((st = dev_upload(&p->d_ell_col, ell.col.data(), ell.col.size(), "upload ell col")) ||
+            (st = dev_upload(&p->d_ell_J, ell.J.data(), ell.J.size(), "upload ell J"))) {
+            release(p);
+            return st;
+        }
+    }
     *out = register_problem(p);
     return OIM_OK;
 }
@@ -263,6 +279,7 @@ __attribute__((visibility("default"))) int oim_problem_info_get(oim_problem h,
     info->sum_J_upper = p->sum_J_upper;
     info->max_instance_n = p->dense ? p->n : p->max_inst_n;
     info->uniform_weight = p->d_sell_uw ? p->uniform_w : 0.f;
+    info->stepwise_row_length = p->d_ell_col ? p->ell_D : 0;
     return OIM_OK;
 }
 

@@ -69,6 +69,13 @@ struct Problem {
     int32_t* d_col = nullptr;
     float* d_J = nullptr;
 
+    // device: the CSR padded to ell_D entries per row (EllImage), for the
+    // stepwise step kernel, or null (single graphs whose rows are of similar
+    // length)
+    int32_t* d_ell_col = nullptr;
+    float* d_ell_J = nullptr;
+    int32_t ell_D = 0;
+
     // instances of a block-diagonal batch (1 for a single graph)
     int32_t n_inst = 1;
     int32_t max_inst_n = 0;  // largest instance (oscillators)
@@ -137,6 +144,29 @@ int validate_blocks(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, i
 // unit-weight image too, or 0.
 void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
                 int32_t n_inst, const int32_t* inst_off, SellImage& out, float uniform_w = 0.f);
+
+// Every row padded to the same length D (the longest row rounded up to 4,
+// at least 4), quads of rows padded to 4 rows, stored quad by quad in
+// groups of 4 entries: entry e = 4t + h of row i = 4m + j at
+// m * 4D + 16t + 4j + h, so the group t of a quad's four rows is 16
+// consecutive words; each row keeps its CSR order.  A padding entry has
+// weight 0 and the row's own column (row n - 1 for rows past n), so a
+// gather over it reads a valid word and adds nothing.  With an entry's
+// position computed from its quad index alone, the stepwise step kernel
+// needs no row bounds before its entry loads.
+struct EllImage {
+    int32_t D = 0;
+    std::vector<int32_t> col;
+    std::vector<float> J;
+};
+
+// Whether a graph takes the padded image: `mode` 0 never, 1 always,
+// otherwise when its rows are of similar length (quads x D / 4 groups of 4
+// entries at most 5/4 of what the CSR loop walks, each quad to its longest
+// row, one group at least).
+bool ell_wanted(int32_t n, const int64_t* row_ptr, int mode);
+void build_ell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+               EllImage& out);
 
 // kernels' host launchers
 int launch_persistent_sparse(const Problem* p, const oim_run_cfg* cfg, const float* K,

@@ -60,9 +60,10 @@ struct CallArgs {
 
 struct StepArgs {
     const int64_t* row_ptr;  // n + 1 entries and 4 copies of nnz
-    const int32_t* col;   // nnz entries and 4 zero entries of padding
+    const int32_t* col;   // nnz entries and 4 zero entries of padding, or the padded image
     const float* J;       // the same
     int64_t nnz;
+    int ell_D;            // entries per row of the padded image (ELL kernels)
     const uint32_t* Uin;  // [np][Rp] phase words of step s
     uint32_t* Uout;       // [np][Rp] phase words of step s + 1
     const CallArgs* call;
@@ -94,7 +95,11 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr
     return (const __attribute__((address_space(1))) T*)p;
 }
 
-template <int QM>
+// ELL: the entries come from the padded row image (every row ell_D
+// entries, padding of weight 0), so their positions follow from the quad
+// index and their loads go out with the per-call block's: two batches of
+// dependent loads per step instead of three.
+template <int QM, bool ELL>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     int qb, rb;
@@ -104,14 +109,15 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int r = rb * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
     const int rs = r < a.R ? r : a.R - 1;  // padding lanes borrow a replica's entries
-    // Every load of a step is issued up front, in three waves with one wait
+    // Every load of a step is issued up front, in batches with one wait
     // each: the per-call block, the quad's row bounds and its own words;
     // then the schedule entries, the seed and the first group of each row's
-    // entries; then the neighbours' words.  Nothing before the store depends
-    // on whether this node's step is still part of the run (a node past the
-    // last step computes on local step 0's entries and writes nothing), and
-    // no select or branch depends on a loaded value, so the compiler keeps
-    // the loads together.
+    // entries; then the neighbours' words (with the padded image the first
+    // two batches are one).  Nothing before the store depends on whether
+    // this node's step is still part of the run (a node past the last step
+    // computes on local step 0's entries and writes nothing), and no select
+    // or branch depends on a loaded value, so the compiler keeps the loads
+    // together.
     const CallArgs& c = *a.call;
     int base = c.base, steps = c.steps, stride = c.sched_stride;
     int64_t step0 = c.step0;
@@ -120,15 +126,128 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const float* Ksp = c.Ks;
     const float* sgp = c.sigma;
     const uint64_t* seedp = c.seeds;
-    int64_t rp[5];  // row_ptr carries 4 entries of padding (empty rows)
+    int64_t eb[4];
+    int len[4];
+    int lmax = 0;
+    if constexpr (ELL) {
+        // group g / 4 of row j of the quad at m * 4D + 4g + 4j (in steps
+        // of 4 entries: g advances the base by 16)
 #pragma unroll
-    for (int j = 0; j < 5; ++j) rp[j] = a.row_ptr[4 * m + j];
-    // one wait for the per-call block and the row bounds together: every
-    // use of them goes through this statement
-    asm(""
-        : "+s"(base), "+s"(steps), "+s"(stride), "+s"(step0), "+s"(dt), "+s"(Kp),
-                   "+s"(Ksp), "+s"(sgp), "+s"(seedp), "+s"(rp[0]), "+s"(rp[1]), "+s"(rp[2]),
-                   "+s"(rp[3]), "+s"(rp[4]));
+        for (int j = 0; j < 4; ++j) {
+            eb[j] = (int64_t)m * 4 * a.ell_D + 4 * j;
+            len[j] = a.ell_D;
+        }
+        lmax = a.ell_D;
+    } else {
+        int64_t rp[5];  // row_ptr carries 4 entries of padding (empty rows)
+#pragma unroll
+        for (int j = 0; j < 5; ++j) rp[j] = a.row_ptr[4 * m + j];
+        // one wait for the per-call block and the row bounds together: every
+        // use of them goes through this statement
+        asm(""
+            : "+s"(base), "+s"(steps), "+s"(stride), "+s"(step0), "+s"(dt), "+s"(Kp),
+                       "+s"(Ksp), "+s"(sgp), "+s"(seedp), "+s"(rp[0]), "+s"(rp[1]), "+s"(rp[2]),
+                       "+s"(rp[3]), "+s"(rp[4]));
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            eb[j] = rp[j];
+            len[j] = (int)(rp[j + 1] - rp[j]);
+            lmax = len[j] > lmax ? len[j] : lmax;
+        }
+    }
+    // The quad's four rows are walked in lock-step, four entries of each
+    // per group, so sixteen neighbour loads are in flight together.  Row
+    // lengths are wave-uniform (every lane is a replica of the same quad), so
+    // a row shorter than the longest costs only its idle slots.  Group t of
+    // row j is the 4 entries from eb + t, clamped to nnz (the arrays carry 4
+    // zero entries past the end, so a group is always in bounds and its
+    // column indexes valid); a slot past the row's end gets weight 0 by
+    // masking its bits, which leaves the sums unchanged (the words are
+    // finite).  The padded image needs neither: its groups are in bounds
+    // and its padding weighs 0.  Each row keeps its order: entries at even
+    // offsets into one partial sum, odd ones into the other.
+    int ci[4][4];
+    uint32_t wb[4][4];
+    auto load_cols = [&](int g) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t base = eb[j] + (ELL ? 4 * g : g);
+            if constexpr (!ELL) base = base < a.nnz ? base : a.nnz;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) ci[j][h] = a.col[base + h];
+        }
+    };
+    auto load_weights = [&](int g) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t base = eb[j] + (ELL ? 4 * g : g);
+            if constexpr (!ELL) base = base < a.nnz ? base : a.nnz;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) wb[j][h] = __float_as_uint(a.J[base + h]);
+        }
+    };
+    auto load_entries = [&](int g) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            int64_t base = eb[j] + (ELL ? 4 * g : g);
+            if constexpr (!ELL) base = base < a.nnz ? base : a.nnz;
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                wb[j][h] = __float_as_uint(a.J[base + h]);
+                ci[j][h] = a.col[base + h];
+            }
+        }
+    };
+    // The first group's four rows' entry loads (scalar loads) are all issued
+    // before the first use: the loaded values pass through empty asm
+    // statements that no load may cross, so nothing that uses them is
+    // scheduled between the loads (each use of a scalar load waits for all
+    // of them).  Later groups are read with vector loads, which complete in
+    // order, and need no such help.
+    auto pin_entries = [&]() {
+        asm(""
+            : "+s"(ci[0][0]), "+s"(ci[0][1]), "+s"(ci[0][2]), "+s"(ci[0][3]),
+              "+s"(ci[1][0]), "+s"(ci[1][1]), "+s"(ci[1][2]), "+s"(ci[1][3]),
+              "+s"(ci[2][0]), "+s"(ci[2][1]), "+s"(ci[2][2]), "+s"(ci[2][3]),
+              "+s"(ci[3][0]), "+s"(ci[3][1]), "+s"(ci[3][2]), "+s"(ci[3][3]),
+              "+s"(wb[0][0]), "+s"(wb[0][1]), "+s"(wb[0][2]), "+s"(wb[0][3]),
+              "+s"(wb[1][0]), "+s"(wb[1][1]), "+s"(wb[1][2]), "+s"(wb[1][3]),
+              "+s"(wb[2][0]), "+s"(wb[2][1]), "+s"(wb[2][2]), "+s"(wb[2][3]),
+              "+s"(wb[3][0]), "+s"(wb[3][1]), "+s"(wb[3][2]), "+s"(wb[3][3]));
+    };
+    uint32_t p[4][4];
+    float w[4][4];
+    auto load_words = [&](int g) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                p[j][h] = a.Uin[(size_t)ci[j][h] * Rp + r];
+                if constexpr (ELL) {
+                    w[j][h] = __uint_as_float(wb[j][h]);
+                } else {
+                    const uint32_t keep = 0u - (uint32_t)(g + h < len[j]);
+                    w[j][h] = __uint_as_float(wb[j][h] & keep);
+                }
+            }
+    };
+    uint32_t u0[4];
+    if constexpr (ELL) {
+        // the first group's columns (the weights are not needed before the
+        // neighbours' words arrive: they go out with them)
+        load_cols(0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
+        // one wait for the per-call block and the columns together
+        asm(""
+            : "+s"(base), "+s"(steps), "+s"(stride), "+s"(step0), "+s"(dt), "+s"(Kp),
+              "+s"(Ksp), "+s"(sgp), "+s"(seedp),
+              "+s"(ci[0][0]), "+s"(ci[0][1]), "+s"(ci[0][2]), "+s"(ci[0][3]),
+              "+s"(ci[1][0]), "+s"(ci[1][1]), "+s"(ci[1][2]), "+s"(ci[1][3]),
+              "+s"(ci[2][0]), "+s"(ci[2][1]), "+s"(ci[2][2]), "+s"(ci[2][3]),
+              "+s"(ci[3][0]), "+s"(ci[3][1]), "+s"(ci[3][2]), "+s"(ci[3][3]));
+        load_weights(0);
+    }
     const int s_node = base + a.k;
     const bool live = s_node < steps;
     const int s = live ? s_node : 0;
@@ -138,68 +257,15 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const float Ksv = global_ptr(Ksp)[so];
     const float sgv = global_ptr(sgp)[so];
     const uint64_t seed = global_ptr(seedp)[rs];
-    int64_t eb[4];
-    int len[4];
-    int lmax = 0;
+    if constexpr (!ELL) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        eb[j] = rp[j];
-        len[j] = (int)(rp[j + 1] - rp[j]);
-        lmax = len[j] > lmax ? len[j] : lmax;
+        for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
+        load_entries(0);
+        pin_entries();
     }
-    uint32_t u0[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
-    // The quad's four rows are walked in lock-step, four entries of each
-    // per group, so sixteen neighbour loads are in flight together.  Row
-    // lengths are wave-uniform (every lane is a replica of the same quad), so
-    // a row shorter than the longest costs only its idle slots.  Group t of
-    // row j is the 4 entries from eb + t, clamped to nnz (the arrays carry 4
-    // zero entries past the end, so a group is always in bounds and its
-    // column indexes valid); a slot past the row's end gets weight 0 by
-    // masking its bits, which leaves the sums unchanged (the words are
-    // finite).  Each row keeps its order: entries at even offsets into one
-    // partial sum, odd ones into the other.
-    uint32_t p[4][4];
-    float w[4][4];
-    auto gather = [&](int g, auto first) {
-        int ci[4][4];
-        uint32_t wb[4][4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            int64_t base = eb[j] + g;
-            base = base < a.nnz ? base : a.nnz;
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                wb[j][h] = __float_as_uint(a.J[base + h]);
-                ci[j][h] = a.col[base + h];
-            }
-        }
-        // The first group's four rows' entry loads (scalar loads) are all
-        // issued before the first use: the loaded values pass through empty
-        // asm statements that no load may cross, so nothing that uses them
-        // is scheduled between the loads (each use of a scalar load waits
-        // for all of them).  Later groups are read with vector loads, which
-        // complete in order, and need no such help.
-        if constexpr (decltype(first)::value) {
-            asm(""
-                : "+s"(ci[0][0]), "+s"(ci[0][1]), "+s"(ci[0][2]), "+s"(ci[0][3]),
-                  "+s"(ci[1][0]), "+s"(ci[1][1]), "+s"(ci[1][2]), "+s"(ci[1][3]),
-                  "+s"(ci[2][0]), "+s"(ci[2][1]), "+s"(ci[2][2]), "+s"(ci[2][3]),
-                  "+s"(ci[3][0]), "+s"(ci[3][1]), "+s"(ci[3][2]), "+s"(ci[3][3]),
-                  "+s"(wb[0][0]), "+s"(wb[0][1]), "+s"(wb[0][2]), "+s"(wb[0][3]),
-                  "+s"(wb[1][0]), "+s"(wb[1][1]), "+s"(wb[1][2]), "+s"(wb[1][3]),
-                  "+s"(wb[2][0]), "+s"(wb[2][1]), "+s"(wb[2][2]), "+s"(wb[2][3]),
-                  "+s"(wb[3][0]), "+s"(wb[3][1]), "+s"(wb[3][2]), "+s"(wb[3][3]));
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                p[j][h] = a.Uin[(size_t)ci[j][h] * Rp + r];
-                const uint32_t keep = 0u - (uint32_t)(g + h < len[j]);
-                w[j][h] = __uint_as_float(wb[j][h] & keep);
-            }
+    auto gather = [&](int g) {
+        load_entries(g);
+        load_words(g);
     };
     float A0[4], B0[4], A1[4], B1[4];
 #pragma unroll
@@ -217,7 +283,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
                 B1[j] = __builtin_fmaf(w[j][h + 1], s1, B1[j]);
             }
     };
-    gather(0, std::true_type{});
+    load_words(0);
     // the quad's normals while the neighbour loads are in flight
     float z[4];
     normals4((uint32_t)m, t, 0u, (uint32_t)seed, (uint32_t)(seed >> 32), z);
@@ -226,7 +292,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     asm volatile("" ::"v"(z[0]), "v"(z[1]), "v"(z[2]), "v"(z[3]) : "memory");
     accumulate();
     for (int g = 4; g < lmax; g += 4) {
-        gather(g, std::false_type{});
+        gather(g);
         accumulate();
     }
     if (!live) return;
@@ -521,13 +587,19 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
     if ((st = check_launch("stepwise_init_kernel"))) return st;
 
     using StepFn = void (*)(StepArgs);
-    StepFn fn = cfg->q == 2 ? stepwise_step_kernel<2>
-                            : cfg->q == 3 ? stepwise_step_kernel<3> : stepwise_step_kernel<0>;
+    const bool ell = p->d_ell_col != nullptr;
+    StepFn fn = ell ? (cfg->q == 2   ? stepwise_step_kernel<2, true>
+                       : cfg->q == 3 ? stepwise_step_kernel<3, true>
+                                     : stepwise_step_kernel<0, true>)
+                    : (cfg->q == 2   ? stepwise_step_kernel<2, false>
+                       : cfg->q == 3 ? stepwise_step_kernel<3, false>
+                                     : stepwise_step_kernel<0, false>);
     StepArgs sa{};
     sa.row_ptr = p->d_row_ptr;
-    sa.col = p->d_col;
-    sa.J = p->d_J;
+    sa.col = ell ? p->d_ell_col : p->d_col;
+    sa.J = ell ? p->d_ell_J : p->d_J;
     sa.nnz = p->nnz;
+    sa.ell_D = p->ell_D;
     sa.call = call;
     sa.n = n;
     sa.R = R;

@@ -252,4 +252,43 @@ void build_sell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const
     });
 }
 
+bool ell_wanted(int32_t n, const int64_t* row_ptr, int mode) {
+    if (mode == 0 || n <= 0) return false;
+    int64_t dmax = 0, csr_groups = 0;
+    for (int32_t m = 0; 4 * m < n; ++m) {
+        int64_t qmax = 0;
+        for (int32_t i = 4 * m; i < std::min(n, 4 * m + 4); ++i)
+            qmax = std::max<int64_t>(qmax, row_ptr[i + 1] - row_ptr[i]);
+        dmax = std::max(dmax, qmax);
+        csr_groups += std::max<int64_t>(1, (qmax + 3) / 4);
+    }
+    const int64_t quads = (n + 3) / 4;
+    if (quads * 4 * std::max<int64_t>(4, (dmax + 3) & ~int64_t(3)) > (int64_t)1 << 26)
+        return false;  // at most 64 Mi entries (512 MiB)
+    if (mode == 1) return true;
+    const int64_t ell_groups = quads * std::max<int64_t>(1, (dmax + 3) / 4);
+    return 4 * ell_groups <= 5 * csr_groups;
+}
+
+void build_ell(int32_t n, const int64_t* row_ptr, const int32_t* col_idx, const float* J,
+               EllImage& out) {
+    int64_t dmax = 0;
+    for (int32_t i = 0; i < n; ++i) dmax = std::max<int64_t>(dmax, row_ptr[i + 1] - row_ptr[i]);
+    const int32_t D = (int32_t)std::max<int64_t>(4, (dmax + 3) & ~int64_t(3));
+    const size_t np = (size_t)(n + 3) / 4 * 4;
+    out.D = D;
+    out.col.assign(np * D, 0);
+    out.J.assign(np * D, 0.f);
+    for (size_t i = 0; i < np; ++i) {
+        const int32_t self = (int32_t)std::min<size_t>(i, (size_t)n - 1);
+        const int64_t b = i < (size_t)n ? row_ptr[i] : 0;
+        const int64_t len = i < (size_t)n ? row_ptr[i + 1] - b : 0;
+        for (int32_t e = 0; e < D; ++e) {
+            const size_t x = (i / 4) * 4 * (size_t)D + (size_t)(e / 4) * 16 + (i % 4) * 4 + e % 4;
+            out.col[x] = e < len ? col_idx[b + e] : self;
+            out.J[x] = e < len ? J[b + e] : 0.f;
+        }
+    }
+}
+
 }  // namespace oim

@@ -1,7 +1,8 @@
-// Exercises the library's host-only argument checks and the sliced-ELL
-// builder on valid and malformed CSR inputs, for a build with the address
+// Exercises the library's host-only argument checks and the sliced-ELL and
+// padded row image builders on valid and malformed CSR inputs, for a build with the address
 // and undefined-behaviour sanitizers (no HIP runtime call is made).  Prints
 // "ok" and exits 0 when every check returned what it should.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <vector>
@@ -120,6 +121,55 @@ int main() {
                     for (int k = 0; k < sp.y; ++k)
                         check((g.col[g.rp[i] + k] > i) == (k >= sp.x), "row split point");
                 }
+    }
+    // the stepwise loop's padded row image: every row of every quad D
+    // entries in CSR order, padding of weight 0 pointing at the row itself
+    for (int32_t n : {1, 5, 64, 301}) {
+        Csr g = random_graph(n, 31u + n, 40);
+        check(ell_wanted(g.n, g.rp.data(), 1) && !ell_wanted(g.n, g.rp.data(), 0), "ell modes");
+        EllImage ell;
+        build_ell(g.n, g.rp.data(), g.col.data(), g.J.data(), ell);
+        int64_t dmax = 0;
+        for (int i = 0; i < n; ++i) dmax = std::max<int64_t>(dmax, g.rp[i + 1] - g.rp[i]);
+        check(ell.D % 4 == 0 && ell.D >= 4 && ell.D >= dmax && ell.D < dmax + 4 + (dmax == 0 ? 4 : 0),
+              "ell row length");
+        const int np = (n + 3) / 4 * 4;
+        check(ell.col.size() == (size_t)np * ell.D && ell.J.size() == ell.col.size(), "ell size");
+        for (int i = 0; i < np; ++i)
+            for (int e = 0; e < ell.D; ++e) {
+                const size_t x = (size_t)(i / 4) * 4 * ell.D + (e / 4) * 16 + (i % 4) * 4 + e % 4;
+                const int64_t len = i < n ? g.rp[i + 1] - g.rp[i] : 0;
+                if (e < len) {
+                    check(ell.col[x] == g.col[g.rp[i] + e] && ell.J[x] == g.J[g.rp[i] + e],
+                          "ell entry");
+                } else {
+                    check(ell.J[x] == 0.f && ell.col[x] == std::min(i, n - 1), "ell padding");
+                }
+            }
+    }
+    {
+        // similar rows take the image by default, a hub row does not
+        Csr ring{8, {0}, {}, {}};
+        for (int i = 0; i < 8; ++i) {
+            ring.col.push_back((i + 7) % 8);
+            ring.col.push_back((i + 1) % 8);
+            ring.J.push_back(1.f);
+            ring.J.push_back(1.f);
+            ring.rp.push_back((int64_t)ring.col.size());
+        }
+        check(ell_wanted(ring.n, ring.rp.data(), 2), "ring takes the padded image");
+        Csr star{64, {0}, {}, {}};
+        for (int j = 1; j < 64; ++j) {
+            star.col.push_back(j);
+            star.J.push_back(1.f);
+        }
+        star.rp.push_back((int64_t)star.col.size());
+        for (int i = 1; i < 64; ++i) {
+            star.col.push_back(0);
+            star.J.push_back(1.f);
+            star.rp.push_back((int64_t)star.col.size());
+        }
+        check(!ell_wanted(star.n, star.rp.data(), 2), "star keeps the CSR");
     }
     // malformed inputs are rejected, never read out of bounds
     Csr g = random_graph(40, 11u, 150);

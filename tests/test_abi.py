@@ -65,7 +65,7 @@ def test_binding_structs_match_the_header(oim):
 
 def test_abi_version_and_status_names(oim):
     from paper_2505_22631_amd import _lib
-    assert oim.oim_abi_version() == _lib.ABI_VERSION == 3
+    assert oim.oim_abi_version() == _lib.ABI_VERSION == 4
     assert _lib.status_name(0) == "OIM_OK"
     assert _lib.status_name(3) == "OIM_E_ASYM"
     assert _lib.status_name(99) == "OIM_E_UNKNOWN"

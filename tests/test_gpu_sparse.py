@@ -382,6 +382,48 @@ def test_graph_beyond_lds_runs_stepwise(dev, oim, orc):
     prob.close()
 
 
+@pytest.mark.parametrize("case", ["torus_auto", "irregular_forced", "ragged_cycle"])
+def test_stepwise_padded_image_is_bit_identical(dev, oim, case, monkeypatch):
+    # the stepwise loop on the padded row image (every row the same length,
+    # padding of weight 0) against the same loop on the CSR: phases, phase
+    # words and every in-run readout equal bit for bit
+    if case == "torus_auto":
+        g, q, R, mode = synth.torus(20, 30, seed=2), 2, 70, None
+    elif case == "irregular_forced":
+        g, q, R, mode = synth.random_small(203, 0.05, seed=7, weights="real"), 3, 5, "1"
+    else:
+        g, q, R, mode = synth.cycle(11), 2, 3, None
+    J = -g.w
+    outs = []
+    for csr in (True, False):
+        if csr:
+            monkeypatch.setenv("OIM_STEPWISE_ELL", "0")
+        elif mode is None:
+            monkeypatch.delenv("OIM_STEPWISE_ELL", raising=False)
+        else:
+            monkeypatch.setenv("OIM_STEPWISE_ELL", mode)
+        prob = _problem(oim, g, J)
+        D = prob.info["stepwise_row_length"]
+        dmax = int(np.diff(g.row_ptr).max())
+        if csr:
+            assert D == 0
+        else:
+            assert D % 4 == 0 and dmax <= D < max(dmax, 1) + 4, D
+        K, Ks, sg = ramp_schedule(prob.info["max_abs_row_sum"], q, 400, 230)
+        th0 = synth.theta0(R, g.n, seed=13)
+        th, ro, words = _gpu_run(oim, prob, th0, K, Ks, sg, synth.seeds(R, 8), q, step0=5,
+                                 readout_every=23, want_best=True, flags=oim.OIM_LOOP_STEPWISE,
+                                 phase=_phase_words(th0))
+        outs.append((th, ro, words))
+        prob.close()
+    (th_c, ro_c, w_c), (th_e, ro_e, w_e) = outs
+    np.testing.assert_array_equal(w_c, w_e)
+    np.testing.assert_array_equal(th_c, th_e)
+    for name in ("trace", "best_h", "best_step", "best_colour"):
+        np.testing.assert_array_equal(ro_c[name], ro_e[name], err_msg=name)
+    print(f"{case}: padded row image bit-identical (n={g.n}, {R} replicas)", flush=True)
+
+
 def test_stepwise_readout_and_resume(dev, oim, orc):
     g = c1_graph()
     J = -g.w
