@@ -29,6 +29,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <new>
 #include <type_traits>
 
@@ -64,6 +65,7 @@ struct StepArgs {
     const float* J;       // the same
     int64_t nnz;
     int ell_D;            // entries per row of the padded image (ELL kernels)
+    uint32_t state_bytes; // bytes of one [np][Rp] buffer of phase words (BUF kernels: < 2^32)
     const uint32_t* Uin;  // [np][Rp] phase words of step s
     uint32_t* Uout;       // [np][Rp] phase words of step s + 1
     const CallArgs* call;
@@ -99,7 +101,8 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr
 // entries, padding of weight 0), so their positions follow from the quad
 // index and their loads go out with the per-call block's: two batches of
 // dependent loads per step instead of three.
-template <int QM, bool ELL>
+
+template <int QM, bool ELL, bool BUF>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
     int qb, rb;
@@ -109,6 +112,33 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int r = rb * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
     const int rs = r < a.R ? r : a.R - 1;  // padding lanes borrow a replica's entries
+    // lane r's word of a row: the row's address is wave-uniform (scalar
+    // arithmetic), the lane's byte offset a 32-bit register shared by every
+    // load and store of the step
+    // Lane r's word of a row of the [np][Rp] state.  BUF: a buffer access
+    // with the row's byte offset in a scalar register (scalar arithmetic on
+    // the wave-uniform row) and the lane's in a vector register shared by
+    // every load and store of the step, so no 64-bit address arithmetic per
+    // lane and access; this needs a state buffer below 4 GiB.  Otherwise a
+    // global access at a 64-bit address.
+    const int roff = r * 4;
+    const uint32_t row_bytes = (uint32_t)Rp * 4u;
+    const __amdgpu_buffer_rsrc_t rin = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.Uin, (short)0, (int)a.state_bytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t rout = __builtin_amdgcn_make_buffer_rsrc(
+        (void*)a.Uout, (short)0, (int)a.state_bytes, 0x00020000);
+    auto lane_word = [&](int row) -> uint32_t {
+        if constexpr (BUF)
+            return __builtin_amdgcn_raw_buffer_load_b32(rin, roff, (int)((uint32_t)row * row_bytes), 0);
+        else
+            return a.Uin[(size_t)row * Rp + r];
+    };
+    auto store_word = [&](int row, uint32_t v) {
+        if constexpr (BUF)
+            __builtin_amdgcn_raw_buffer_store_b32(v, rout, roff, (int)((uint32_t)row * row_bytes), 0);
+        else
+            a.Uout[(size_t)row * Rp + r] = v;
+    };
     // Every load of a step is issued up front, in batches with one wait
     // each: the per-call block, the quad's row bounds and its own words;
     // then the schedule entries, the seed and the first group of each row's
@@ -222,7 +252,10 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
         for (int j = 0; j < 4; ++j)
 #pragma unroll
             for (int h = 0; h < 4; ++h) {
-                p[j][h] = a.Uin[(size_t)ci[j][h] * Rp + r];
+                // the column is wave-uniform (every lane is a replica of the
+                // same quad); later groups' columns arrive in vector
+                // registers, so say so
+                p[j][h] = lane_word(__builtin_amdgcn_readfirstlane(ci[j][h]));
                 if constexpr (ELL) {
                     w[j][h] = __uint_as_float(wb[j][h]);
                 } else {
@@ -237,7 +270,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
         // neighbours' words arrive: they go out with them)
         load_cols(0);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
+        for (int j = 0; j < 4; ++j) u0[j] = lane_word(4 * m + j);
         // one wait for the per-call block and the columns together
         asm(""
             : "+s"(base), "+s"(steps), "+s"(stride), "+s"(step0), "+s"(dt), "+s"(Kp),
@@ -259,7 +292,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const uint64_t seed = global_ptr(seedp)[rs];
     if constexpr (!ELL) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) u0[j] = a.Uin[(size_t)(4 * m + j) * Rp + r];
+        for (int j = 0; j < 4; ++j) u0[j] = lane_word(4 * m + j);
         load_entries(0);
         pin_entries();
     }
@@ -307,7 +340,7 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
         const float A = A0[j] + A1[j], B = B0[j] + B1[j];
         const float coup = os * A - oc * B;
         const float drift = kc * coup + ks * sin_q<QM>(os, oc, u0[j], q);
-        a.Uout[(size_t)i * Rp + r] = advance(u0[j], __builtin_fmaf(ns, z[j], drift));
+        store_word(i, advance(u0[j], __builtin_fmaf(ns, z[j], drift)));
     }
 }
 
@@ -588,18 +621,28 @@ int run_stepwise(Problem* p, const oim_run_cfg* cfg, const float* K, const float
 
     using StepFn = void (*)(StepArgs);
     const bool ell = p->d_ell_col != nullptr;
-    StepFn fn = ell ? (cfg->q == 2   ? stepwise_step_kernel<2, true>
-                       : cfg->q == 3 ? stepwise_step_kernel<3, true>
-                                     : stepwise_step_kernel<0, true>)
-                    : (cfg->q == 2   ? stepwise_step_kernel<2, false>
-                       : cfg->q == 3 ? stepwise_step_kernel<3, false>
-                                     : stepwise_step_kernel<0, false>);
+    // buffer addressing for states below 4 GiB (OIM_STEPWISE_GLOBAL_ADDR=1
+    // takes the 64-bit global addressing of larger states for any size)
+    bool buf = cells * 4 < ((size_t)1 << 32);
+    if (const char* env = getenv("OIM_STEPWISE_GLOBAL_ADDR"))
+        if (atoi(env) != 0) buf = false;
+    static const StepFn kStep[2][2][3] = {
+        {{stepwise_step_kernel<0, false, false>, stepwise_step_kernel<2, false, false>,
+          stepwise_step_kernel<3, false, false>},
+         {stepwise_step_kernel<0, false, true>, stepwise_step_kernel<2, false, true>,
+          stepwise_step_kernel<3, false, true>}},
+        {{stepwise_step_kernel<0, true, false>, stepwise_step_kernel<2, true, false>,
+          stepwise_step_kernel<3, true, false>},
+         {stepwise_step_kernel<0, true, true>, stepwise_step_kernel<2, true, true>,
+          stepwise_step_kernel<3, true, true>}}};
+    StepFn fn = kStep[ell][buf][cfg->q == 2 ? 1 : cfg->q == 3 ? 2 : 0];
     StepArgs sa{};
     sa.row_ptr = p->d_row_ptr;
     sa.col = ell ? p->d_ell_col : p->d_col;
     sa.J = ell ? p->d_ell_J : p->d_J;
     sa.nnz = p->nnz;
     sa.ell_D = p->ell_D;
+    sa.state_bytes = buf ? (uint32_t)(cells * 4) : 0u;
     sa.call = call;
     sa.n = n;
     sa.R = R;

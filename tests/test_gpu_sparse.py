@@ -383,10 +383,11 @@ def test_graph_beyond_lds_runs_stepwise(dev, oim, orc):
 
 
 @pytest.mark.parametrize("case", ["torus_auto", "irregular_forced", "ragged_cycle"])
-def test_stepwise_padded_image_is_bit_identical(dev, oim, case, monkeypatch):
-    # the stepwise loop on the padded row image (every row the same length,
-    # padding of weight 0) against the same loop on the CSR: phases, phase
-    # words and every in-run readout equal bit for bit
+def test_stepwise_forms_are_bit_identical(dev, oim, case, monkeypatch):
+    # the stepwise loop's four forms: entries from the CSR or from the padded
+    # row image (every row the same length, padding of weight 0), state
+    # words addressed as buffer offsets or at 64-bit global addresses;
+    # phases, phase words and every in-run readout equal bit for bit
     if case == "torus_auto":
         g, q, R, mode = synth.torus(20, 30, seed=2), 2, 70, None
     elif case == "irregular_forced":
@@ -395,13 +396,17 @@ def test_stepwise_padded_image_is_bit_identical(dev, oim, case, monkeypatch):
         g, q, R, mode = synth.cycle(11), 2, 3, None
     J = -g.w
     outs = []
-    for csr in (True, False):
+    for csr, global_addr in ((True, False), (False, False), (False, True), (True, True)):
         if csr:
             monkeypatch.setenv("OIM_STEPWISE_ELL", "0")
         elif mode is None:
             monkeypatch.delenv("OIM_STEPWISE_ELL", raising=False)
         else:
             monkeypatch.setenv("OIM_STEPWISE_ELL", mode)
+        if global_addr:
+            monkeypatch.setenv("OIM_STEPWISE_GLOBAL_ADDR", "1")
+        else:
+            monkeypatch.delenv("OIM_STEPWISE_GLOBAL_ADDR", raising=False)
         prob = _problem(oim, g, J)
         D = prob.info["stepwise_row_length"]
         dmax = int(np.diff(g.row_ptr).max())
@@ -416,12 +421,13 @@ def test_stepwise_padded_image_is_bit_identical(dev, oim, case, monkeypatch):
                                  phase=_phase_words(th0))
         outs.append((th, ro, words))
         prob.close()
-    (th_c, ro_c, w_c), (th_e, ro_e, w_e) = outs
-    np.testing.assert_array_equal(w_c, w_e)
-    np.testing.assert_array_equal(th_c, th_e)
-    for name in ("trace", "best_h", "best_step", "best_colour"):
-        np.testing.assert_array_equal(ro_c[name], ro_e[name], err_msg=name)
-    print(f"{case}: padded row image bit-identical (n={g.n}, {R} replicas)", flush=True)
+    th_c, ro_c, w_c = outs[0]
+    for th_e, ro_e, w_e in outs[1:]:
+        np.testing.assert_array_equal(w_c, w_e)
+        np.testing.assert_array_equal(th_c, th_e)
+        for name in ("trace", "best_h", "best_step", "best_colour"):
+            np.testing.assert_array_equal(ro_c[name], ro_e[name], err_msg=name)
+    print(f"{case}: four stepwise forms bit-identical (n={g.n}, {R} replicas)", flush=True)
 
 
 def test_stepwise_readout_and_resume(dev, oim, orc):
