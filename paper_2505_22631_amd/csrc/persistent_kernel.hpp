@@ -289,7 +289,7 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
 #pragma unroll
                     for (int jj = 0; jj < RPL; ++jj) A[jj] = B[jj] = 0.f;
                     for (int e4 = 0; e4 < D4; e4 += U4) {
-                        if (e4 > 0) load_iter(e4);
+                        if (RPL == 4 && e4 > 0) load_iter(e4);
                         float2 p[U4][RPL][4];
 #pragma unroll
                         for (int h = 0; h < U4; ++h)
@@ -302,6 +302,12 @@ __global__ __launch_bounds__(TB) void persistent_sparse_kernel(PersistArgs a) {
                                     p[h][jj][3] = sc_at(smem, v[jj][h].w);
                                 }
                             }
+                        // split rows (long rows, several iterations): the next
+                        // iteration's offsets are loaded now, their L2 round
+                        // trip under this iteration's LDS reads and sums (the
+                        // reads above have taken their addresses); whole-quad
+                        // shapes keep their registers for occupancy
+                        if (RPL < 4 && e4 + U4 < D4) load_iter(e4 + U4);
 #pragma unroll
                         for (int h = 0; h < U4; ++h) {
                             if (h == 0 || e4 + h < D4) {
