@@ -70,6 +70,26 @@ def source_hash(sources) -> str:
     return h.hexdigest()[:16]
 
 
+def _launch_shape(args, prob, q):
+    """--launch BxSxL: that launch shape of the LDS-resident kernel (threads,
+    slices per wave, rows per lane) instead of the autotuner's choice, so
+    counters can be taken on a given shape; None without it."""
+    if not getattr(args, "launch", None):
+        return None
+    import paper_2505_22631_amd as oim
+    b, s, l = (int(x) for x in args.launch.lower().split("x"))
+    oim.oim_set_tuning(prob.handle, q, b, s, l)
+    return {"block": b, "slices_per_wave": s, "rows_per_lane": l}
+
+
+def _shape_suffix(R, launch):
+    """Profile key suffix of a launch of the LDS-resident kernel: replicas and
+    launch shape (threads x slices per wave x rows per lane), since counters
+    such as register-spill traffic depend on the shape the tuner picked."""
+    return (f"R{R}_{launch['block']}x{launch['slices_per_wave']}"
+            f"x{launch.get('rows_per_lane', 4)}")
+
+
 def _profile_value(name, key):
     """A figure from a committed profile summary (`key: value ... source_sha256:
     hash`), if it was taken on the kernel sources as they are now."""
@@ -270,8 +290,8 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
     best_step = torch.empty(R, dtype=torch.int32, device=dev)
     colour = torch.empty((R, g.n), dtype=torch.int8, device=dev)
     stream = torch.cuda.current_stream()
-    launch, _ = tune.tuned(prob, th_init, dK, dKs, dsg, seeds, q=q, dt=DT,
-                           trial_steps=min(steps, 500))
+    launch = _launch_shape(args, prob, q) or tune.tuned(
+        prob, th_init, dK, dKs, dsg, seeds, q=q, dt=DT, trial_steps=min(steps, 500))[0]
     cuts = []
 
     def solve(ev):
@@ -406,8 +426,9 @@ def maxcut_workload(args, name, g, R, steps, M, label, timed_steps, plain_replic
                                     "rows_per_lane": launch.get("rows_per_lane", 4)}})
     prof = name if name in PROFILES else None
     if prof:
-        roof["traffic"] = _profile_value(prof, f"traffic_bytes_per_launch_R{R}")
-        valu = _profile_value(prof, f"valu_busy_frac_R{R}")
+        sfx = _shape_suffix(R, launch)
+        roof["traffic"] = _profile_value(prof, "traffic_bytes_per_launch_" + sfx)
+        valu = _profile_value(prof, "valu_busy_frac_" + sfx)
         if valu is not None:
             roof["valu_busy_frac"] = valu
     out = {
@@ -477,7 +498,8 @@ def colouring_workload(args):
     best_step = torch.empty(R * count, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     edges = np.array([g.nnz // 2 for g in graphs], np.float64)
-    launch, _ = tune.tuned(prob, th_init, dK, dKs, dsg, seeds, q=q, dt=DT, trial_steps=500)
+    launch = _launch_shape(args, prob, q) or tune.tuned(
+        prob, th_init, dK, dKs, dsg, seeds, q=q, dt=DT, trial_steps=500)[0]
 
     def solve(ev):
         theta.copy_(th_init)
@@ -603,8 +625,9 @@ def colouring_workload(args):
                         {"launch": {"block": launch["block"],
                                     "slices_per_wave": launch["slices_per_wave"],
                                     "rows_per_lane": launch.get("rows_per_lane", 4)}})
-    roof["traffic"] = _profile_value("colouring", f"traffic_bytes_per_launch_R{R}")
-    valu = _profile_value("colouring", f"valu_busy_frac_R{R}")
+    sfx = _shape_suffix(R, launch)
+    roof["traffic"] = _profile_value("colouring", "traffic_bytes_per_launch_" + sfx)
+    valu = _profile_value("colouring", "valu_busy_frac_" + sfx)
     if valu is not None:
         roof["valu_busy_frac"] = valu
     out = {
@@ -988,6 +1011,10 @@ def main():
                     help="replicas per graph in the colouring batch")
     ap.add_argument("--stepwise", type=int, default=1,
                     help="also time the torus solve on the stepwise hipGraph loop (0: skip)")
+    ap.add_argument("--launch", default="",
+                    help="BxSxL: run the torus, G(800, 0.06) and colouring workloads with "
+                         "that launch shape (threads x slices per wave x rows per lane) "
+                         "instead of the autotuner's (for counter runs on a given shape)")
     ap.add_argument("--stepwise-steps", type=int, default=0,
                     help="EM steps of the stepwise solve (0: the whole schedule; fewer for "
                          "counter runs, which serialise every step kernel)")
