@@ -97,11 +97,12 @@ __device__ __forceinline__ const __attribute__((address_space(1))) T* global_ptr
     return (const __attribute__((address_space(1))) T*)p;
 }
 
-// ELL: the entries come from the padded row image (every row ell_D
-// entries, padding of weight 0), so their positions follow from the quad
-// index and their loads go out with the per-call block's: two batches of
-// dependent loads per step instead of three.
-
+// One Euler-Maruyama step of one quad for 64 replicas per wave.  ELL: the
+// entries come from the padded row image (every row ell_D entries, padding
+// of weight 0), so their positions follow from the quad index and their
+// loads go out with the per-call block's: two batches of dependent loads per
+// step instead of three.  BUF: the state words are addressed as buffer
+// offsets (state buffers below 4 GiB), else at 64-bit global addresses.
 template <int QM, bool ELL, bool BUF>
 __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int lane = threadIdx.x & 63;
@@ -112,9 +113,6 @@ __global__ __launch_bounds__(256) void stepwise_step_kernel(StepArgs a) {
     const int r = rb * 64 + lane;
     const int Rp = a.Rp, q = QM ? QM : a.q;
     const int rs = r < a.R ? r : a.R - 1;  // padding lanes borrow a replica's entries
-    // lane r's word of a row: the row's address is wave-uniform (scalar
-    // arithmetic), the lane's byte offset a 32-bit register shared by every
-    // load and store of the step
     // Lane r's word of a row of the [np][Rp] state.  BUF: a buffer access
     // with the row's byte offset in a scalar register (scalar arithmetic on
     // the wave-uniform row) and the lane's in a vector register shared by
