@@ -393,7 +393,8 @@ def test_stepwise_forms_are_bit_identical(dev, oim, case, monkeypatch):
     elif case == "irregular_forced":
         g, q, R, mode = synth.random_small(203, 0.05, seed=7, weights="real"), 3, 5, "1"
     else:
-        g, q, R, mode = synth.cycle(11), 2, 3, None
+        # generic q (sin(q theta) from the phase word), ragged last quad
+        g, q, R, mode = synth.cycle(11), 5, 3, None
     J = -g.w
     outs = []
     for csr, global_addr in ((True, False), (False, False), (False, True), (True, True)):
