@@ -59,6 +59,7 @@ PROFILES = {
     "gnp800": ("profiles/persistent_sparse_kernel__gnp800_R256.md", SPARSE_SOURCES),
     "colouring": ("profiles/persistent_sparse_kernel__colouring1024_q3.md", SPARSE_SOURCES),
     "sk4096": ("profiles/dense_step_kernel__sk4096_R512.md", DENSE_SOURCES),
+    "sk20000": ("profiles/dense_step_kernel__sk20000_R512.md", DENSE_SOURCES),
 }
 
 
@@ -725,18 +726,21 @@ def dense_workload(args, n=4096, fp32=False):
     # the BF16x3 coupling, one FP32 product for the FP32 coupling
     flops_step = (1.0 if fp32 else 3.0) * 2.0 * n * n * 2 * R
     peak = MFMA_FP32_PEAK_TFLOPS if fp32 else MFMA_BF16_PEAK_TFLOPS
+    # counters from the profile of this size and precision, when there is one
+    prof = {4096: "sk4096", 20000: "sk20000"}.get(n)
+    prec = "fp32" if fp32 else "bf16x3"
     achieved = flops_step * steps / (run_ms * 1e-3) / 1e12
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
             "frac": achieved / peak,
-            "traffic": (_profile_value("sk4096", "traffic_bytes_per_step_bf16x3")
-                        if n == 4096 and not fp32 else None),
+            "traffic": (_profile_value(prof, "traffic_bytes_per_step_" + prec)
+                        if prof else None),
             "kernel": ("dense_step32_kernel" if fp32 else "dense_step_kernel")
                       + " (per step, epilogue fused)",
             "kernel_ms_per_em_step": run_ms / steps, "flops_per_step": flops_step,
             "useful_flops_per_step": 4.0 * n * n * R,
             "useful_frac": 4.0 * n * n * R * steps / (run_ms * 1e-3) / 1e12 / peak}
-    busy = _profile_value("sk4096", "mfma_busy_frac_" + ("fp32" if fp32 else "bf16x3"))
-    if busy is not None and n == 4096:
+    busy = _profile_value(prof, "mfma_busy_frac_" + prec) if prof else None
+    if busy is not None:
         roof["mfma_busy_frac"] = busy
     out = {"value": eu / (wall_ms * 1e-3), "unit": "edge-updates/s", "ms_per_solve": wall_ms,
            "kernel_ms": run_ms, "dtype": "f32" if fp32 else "bf16x3",
