@@ -50,6 +50,8 @@ SPARSE_SOURCES = ["paper_2505_22631_amd/csrc/sparse_persistent.hip",
                   "paper_2505_22631_amd/csrc/tree.hpp"]
 DENSE_SOURCES = ["paper_2505_22631_amd/csrc/dense.hip", "paper_2505_22631_amd/csrc/noise.hpp",
                  "paper_2505_22631_amd/csrc/phase.hpp"]
+ADJOINT_SOURCES = ["paper_2505_22631_amd/csrc/adjoint.hip", "paper_2505_22631_amd/csrc/noise.hpp",
+                   "paper_2505_22631_amd/csrc/phase.hpp"]
 STEPWISE_SOURCES = ["paper_2505_22631_amd/csrc/stepwise.hip",
                     "paper_2505_22631_amd/csrc/noise.hpp", "paper_2505_22631_amd/csrc/phase.hpp",
                     "paper_2505_22631_amd/csrc/tree.hpp"]
@@ -60,6 +62,7 @@ PROFILES = {
     "colouring": ("profiles/persistent_sparse_kernel__colouring1024_q3.md", SPARSE_SOURCES),
     "sk4096": ("profiles/dense_step_kernel__sk4096_R512.md", DENSE_SOURCES),
     "sk20000": ("profiles/dense_step_kernel__sk20000_R512.md", DENSE_SOURCES),
+    "adjoint": ("profiles/adjoint_kernels__128xG2000_deg10.md", ADJOINT_SOURCES),
 }
 
 
@@ -853,7 +856,8 @@ def adjoint_workload(args):
         "forward_ms": t_f, "backward_ms": t_b,
         "roofline": {"bound": "hbm", "achieved": bps * steps / (t_f * 1e-3) / 1e9,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": bps * steps / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS, "traffic": None,
+                     "frac": bps * steps / (t_f * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                     "traffic": _profile_value("adjoint", "traffic_bytes_per_forward_launch"),
                      "kernel": "adjoint_forward_kernel", "kernel_ms": t_f,
                      "bytes_per_em_step": bps,
                      "backward_frac": 3.0 * bps * steps / (t_b * 1e-3) / 1e9 / HBM_PEAK_GBS},
