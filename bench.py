@@ -98,7 +98,10 @@ def _profile_value(name, key):
     """A figure from a committed profile summary (`key: value ... source_sha256:
     hash`), if it was taken on the kernel sources as they are now."""
     path, sources = PROFILES[name]
-    want = source_hash(sources)
+    try:
+        want = source_hash(sources)
+    except OSError:  # sources not at hand: the figure cannot be matched to them
+        return None
     try:
         for line in open(os.path.join(ROOT, path)):
             if line.startswith(key + ":"):

@@ -32,6 +32,7 @@
 
 #include <cstdlib>
 #include <cstring>
+#include <type_traits>
 
 #include "internal.hpp"
 #include "noise.hpp"
@@ -159,7 +160,8 @@ struct Rows {
 // (s, c, s lam, c lam): A = sum J c_j, B = sum J s_j and, if LAM,
 // Cl = sum J c_j lam_j, Dl = sum J s_j lam_j.
 template <bool LAM, int MODE>
-__device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, int i,
+__device__ __forceinline__ void gather(const Rows<MODE>& g,
+                                       const std::conditional_t<LAM, float4, float2>* tab, int i,
                                        float& A, float& B, float& Cl, float& Dl) {
     const int64_t e0 = g.begin(i), e1 = g.end(i);
     float A0 = 0.f, B0 = 0.f, C0 = 0.f, D0 = 0.f, A1 = 0.f, B1 = 0.f, C1 = 0.f, D1 = 0.f;
@@ -191,7 +193,7 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
         } else {
             float2 pv[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) pv[k] = *reinterpret_cast<const float2*>(tab + jj[k]);
+            for (int k = 0; k < 8; ++k) pv[k] = tab[jj[k]];
 #pragma unroll
             for (int k = 0; k < 8; k += 2) {
                 A0 = __builtin_fmaf(ww[k], pv[k].y, A0);
@@ -217,8 +219,8 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
             C1 = __builtin_fmaf(w1, p1.w, C1);
             D1 = __builtin_fmaf(w1, p1.z, D1);
         } else {
-            const float2 p0 = *reinterpret_cast<const float2*>(tab + j0);
-            const float2 p1 = *reinterpret_cast<const float2*>(tab + j1);
+            const float2 p0 = tab[j0];
+            const float2 p1 = tab[j1];
             A0 = __builtin_fmaf(w0, p0.y, A0);
             B0 = __builtin_fmaf(w0, p0.x, B0);
             A1 = __builtin_fmaf(w1, p1.y, A1);
@@ -236,7 +238,7 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
             C0 = __builtin_fmaf(w0, p0.w, C0);
             D0 = __builtin_fmaf(w0, p0.z, D0);
         } else {
-            const float2 p0 = *reinterpret_cast<const float2*>(tab + j0);
+            const float2 p0 = tab[j0];
             A0 = __builtin_fmaf(w0, p0.y, A0);
             B0 = __builtin_fmaf(w0, p0.x, B0);
         }
@@ -255,7 +257,7 @@ __device__ __forceinline__ void gather(const Rows<MODE>& g, const float4* tab, i
 // is the same for the whole wave.  Per row the partial sums take the even and
 // the odd entries in order, exactly as gather does, and a pad adds +-0 to a
 // partial sum that is never -0: the results are the same bits.
-__device__ __forceinline__ void gather_quad_ell(const Rows<kEllUnit>& g, const float4* tab, int k,
+__device__ __forceinline__ void gather_quad_ell(const Rows<kEllUnit>& g, const float2* tab, int k,
                                                 int lane, float (&A)[4], float (&B)[4]) {
     const int D4 = g.ellD[k] >> 2;
     const uint2* img = reinterpret_cast<const uint2*>(g.ell + g.ellBase[k]) + lane;
@@ -273,7 +275,7 @@ __device__ __forceinline__ void gather_quad_ell(const Rows<kEllUnit>& g, const f
                 const uint32_t word = t < 2 ? v[j].x : v[j].y;
                 const uint32_t c = (t & 1) ? word >> 16 : word & 0xffffu;
                 const float wt = (c & 0x8000u) ? -1.0f : 1.0f;
-                const float2 p = *reinterpret_cast<const float2*>(tab + (c & 0x7fffu));
+                const float2 p = tab[c & 0x7fffu];
                 if (t & 1) {
                     a1[j] = __builtin_fmaf(wt, p.y, a1[j]);
                     b1[j] = __builtin_fmaf(wt, p.x, b1[j]);
@@ -291,14 +293,14 @@ __device__ __forceinline__ void gather_quad_ell(const Rows<kEllUnit>& g, const f
 }
 
 // Writes (s, c) of the thread's oscillators into a table.
-__device__ __forceinline__ void put_sc(const Ctx& x, float4* tab, const uint32_t (&u)[kAdjQPT][4]) {
+__device__ __forceinline__ void put_sc(const Ctx& x, float2* tab, const uint32_t (&u)[kAdjQPT][4]) {
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k) {
         const int m = threadIdx.x + k * kAdjTB;
         if (m >= x.nq) break;
 #pragma unroll
         for (int j = 0; j < 4; ++j)
-            *reinterpret_cast<float2*>(tab + 4 * m + j) = make_float2(sin_turn(u[k][j]), cos_turn(u[k][j]));
+            tab[4 * m + j] = make_float2(sin_turn(u[k][j]), cos_turn(u[k][j]));
     }
 }
 
@@ -306,7 +308,7 @@ __device__ __forceinline__ void put_sc(const Ctx& x, float4* tab, const uint32_t
 // neighbour (s, c) from tin and writing the new (s, c) into tout.
 template <int QM, int MODE>
 __device__ __forceinline__ void fwd_step(const AdjArgs& a, const Ctx& x, const Rows<MODE>& g, int s,
-                                         const float4* tin, float4* tout,
+                                         const float2* tin, float2* tout,
                                          uint32_t (&u)[kAdjQPT][4]) {
     const int q = QM ? QM : a.q;
     const uint32_t t = (uint32_t)(a.step0 + s);
@@ -372,6 +374,16 @@ __device__ __forceinline__ float wave_sum(float v) {
     return v;
 }
 
+// The same two tables as (s, c) alone, 8 bytes per oscillator from the start
+// of each table's space: the forward steps read only (s, c), and at an
+// 8-byte stride a gather's random reads spread over all LDS banks (at the
+// 16-byte stride of the full entries, over half of them).  Entry tabN of
+// each stays zero (padding of the row image points there); the full entries
+// it overlaps are written before the backward reads them.
+__device__ __forceinline__ float2* tab2_of(unsigned char* smem, int tabN, int k) {
+    return reinterpret_cast<float2*>(smem) + (size_t)k * 2 * (tabN + 1);
+}
+
 // Dynamic LDS: two tables of tabN + 1 float4 (entry tabN of each stays zero),
 // then (CSR in LDS) the instance's row offsets, 16-bit column indices and FP32
 // weights, or (ELL_UNIT) per-slice lengths and the padded row image.  Fills
@@ -382,7 +394,10 @@ __device__ __forceinline__ Rows<MODE> setup_rows(const AdjArgs& a, const Ctx& x,
     g.a = &a;
     g.off = x.off;
     float4* tabs = reinterpret_cast<float4*>(smem);
-    if (threadIdx.x < 2) tabs[(size_t)threadIdx.x * (a.tabN + 1) + a.tabN] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (threadIdx.x < 2) {
+        tabs[(size_t)threadIdx.x * (a.tabN + 1) + a.tabN] = make_float4(0.f, 0.f, 0.f, 0.f);
+        tab2_of(smem, a.tabN, threadIdx.x)[a.tabN] = make_float2(0.f, 0.f);
+    }
     unsigned char* p = smem + (size_t)32 * (a.tabN + 1);
     if constexpr (MODE == kEllUnit) {
         // slice s holds quads 64 s .. 64 s + 63, i.e. the quads of wave
@@ -471,8 +486,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
     __shared__ double red[kAdjWaves];
     const Ctx x = make_ctx(a);
     const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
-    float4* const tabs = reinterpret_cast<float4*>(smem);
-    auto tab = [&](int k) { return tabs + (size_t)k * (a.tabN + 1); };
+    auto tab = [&](int k) { return tab2_of(smem, a.tabN, k); };
     uint32_t u[kAdjQPT][4];
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k)
@@ -489,7 +503,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_forward_kernel(AdjArgs a) {
         __syncthreads();
     }
     // relaxed cut of the final phases: sum_i (c_i A_i + s_i B_i - sum_j J_ij) / 4
-    const float4* fin = tab(a.steps & 1);
+    const float2* fin = tab(a.steps & 1);
     double part = 0.0;
 #pragma unroll
     for (int k = 0; k < kAdjQPT; ++k) {
@@ -537,8 +551,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_recompute_kernel(AdjArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     const Ctx x = make_ctx(a);
     const Rows<MODE> g = setup_rows<MODE>(a, x, smem);
-    float4* const tabs = reinterpret_cast<float4*>(smem);
-    auto tab = [&](int k) { return tabs + (size_t)k * (a.tabN + 1); };
+    auto tab = [&](int k) { return tab2_of(smem, a.tabN, k); };
     const int sg = a.cur_seg;
     const int t0 = sg * a.C;
     const int t1 = t0 + a.C < a.steps ? t0 + a.C : a.steps;
@@ -583,7 +596,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_segment_kernel(AdjArgs a) {
     if (sg == a.nseg - 1) {
         // lam_T from the final phases
         load_words(a, x, a.seg, t1 - t0, u);
-        put_sc(x, tab(p), u);
+        put_sc(x, tab2_of(smem, a.tabN, p), u);
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < kAdjQPT; ++k) {
@@ -594,7 +607,7 @@ __global__ __launch_bounds__(kAdjTB) void adjoint_segment_kernel(AdjArgs a) {
                 lam[k][j] = 0.f;
                 if (m >= x.nq || i >= x.nb) continue;
                 float A, B, Cl, Dl;
-                gather<false>(g, tab(p), i, A, B, Cl, Dl);
+                gather<false>(g, tab2_of(smem, a.tabN, p), i, A, B, Cl, Dl);
                 const float si = sin_turn(u[k][j]), ci = cos_turn(u[k][j]);
                 lam[k][j] = -0.5f * (si * A - ci * B);
             }
