@@ -126,6 +126,9 @@ __device__ __forceinline__ size_t slot_index(const AdjArgs& a, const Ctx& x, int
 template <int MODE>
 struct Rows {
     static constexpr bool kGlobal = MODE == kCsrGlobal || MODE == kEllUnit;
+    // entry positions: 64-bit in the global CSR, 32-bit in the LDS copy (no
+    // 64-bit compares and adds in the gathers' loops)
+    using Idx = std::conditional_t<kGlobal, int64_t, int32_t>;
     const AdjArgs* a;
     int off;
     const int32_t* rp;    // LDS row offsets [nb + 1]
@@ -135,13 +138,15 @@ struct Rows {
     // padded row length and the slice's offset in the image (wave-uniform)
     const uint16_t* ell;
     int ellD[kAdjQPT], ellBase[kAdjQPT];
-    __device__ __forceinline__ int64_t begin(int i) const {
-        return kGlobal ? a->row_ptr[off + i] : (int64_t)rp[i];
+    __device__ __forceinline__ Idx begin(int i) const {
+        if constexpr (kGlobal) return a->row_ptr[off + i];
+        else return rp[i];
     }
-    __device__ __forceinline__ int64_t end(int i) const {
-        return kGlobal ? a->row_ptr[off + i + 1] : (int64_t)rp[i + 1];
+    __device__ __forceinline__ Idx end(int i) const {
+        if constexpr (kGlobal) return a->row_ptr[off + i + 1];
+        else return rp[i + 1];
     }
-    __device__ __forceinline__ void edge(int64_t e, int& j, float& wt) const {
+    __device__ __forceinline__ void edge(Idx e, int& j, float& wt) const {
         if constexpr (kGlobal) {
             j = a->col[e] - off;
             wt = a->J[e];
@@ -163,9 +168,10 @@ template <bool LAM, int MODE>
 __device__ __forceinline__ void gather(const Rows<MODE>& g,
                                        const std::conditional_t<LAM, float4, float2>* tab, int i,
                                        float& A, float& B, float& Cl, float& Dl) {
-    const int64_t e0 = g.begin(i), e1 = g.end(i);
+    using Idx = typename Rows<MODE>::Idx;
+    const Idx e0 = g.begin(i), e1 = g.end(i);
     float A0 = 0.f, B0 = 0.f, C0 = 0.f, D0 = 0.f, A1 = 0.f, B1 = 0.f, C1 = 0.f, D1 = 0.f;
-    int64_t e = e0;
+    Idx e = e0;
     // eight edges at a time: eight index reads, then eight table reads, in
     // flight together; edges at even offsets from e0 go to the first partial
     // sums and odd ones to the second, in order, exactly as in the pairwise
