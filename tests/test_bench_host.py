@@ -1,5 +1,6 @@
 """Host-side helpers of bench.py (no GPU): the 1-flip descent that polishes
-the reference cut, checked against exhaustive single-flip improvement."""
+the reference cut, checked against exhaustive single-flip improvement, and
+the lookup of profile figures by launch shape and source hash."""
 import itertools
 import os
 import sys
@@ -66,3 +67,24 @@ def test_oracle_sample_longer_than_the_schedule_reruns_it(monkeypatch):
     s1 = int(out["sample"].split("and 1 replica x ")[1].split(" steps")[0])
     legs = [c for c in calls if c[2] == 1][1:]  # after the 2-step probe
     assert sum(c[1] for c in legs) == s1
+
+
+def test_profile_figures_are_keyed_by_launch_shape_and_sources(tmp_path, monkeypatch):
+    # a figure is used only for the launch shape it was measured on and only
+    # while the kernel sources hash as recorded; missing sources give none
+    assert bench._shape_suffix(256, {"block": 768, "slices_per_wave": 4,
+                                     "rows_per_lane": 4}) == "R256_768x4x4"
+    assert bench._shape_suffix(1, {"block": 1024, "slices_per_wave": 1}) == "R1_1024x1x4"
+    src = tmp_path / "k.hip"
+    src.write_text("kernel v1\n")
+    prof = tmp_path / "p.md"
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setitem(bench.PROFILES, "t", ("p.md", ["k.hip"]))
+    h = bench.source_hash(["k.hip"])
+    prof.write_text(f"traffic_bytes_per_launch_R256_768x4x4: 123 source_sha256: {h}\n")
+    assert bench._profile_value("t", "traffic_bytes_per_launch_R256_768x4x4") == 123.0
+    assert bench._profile_value("t", "traffic_bytes_per_launch_R256_1024x3x4") is None
+    src.write_text("kernel v2\n")
+    assert bench._profile_value("t", "traffic_bytes_per_launch_R256_768x4x4") is None
+    src.unlink()
+    assert bench._profile_value("t", "traffic_bytes_per_launch_R256_768x4x4") is None
